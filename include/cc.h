@@ -1,0 +1,191 @@
+/*
+ * cc.h -- C ABI of the MI355X (gfx950) correlation-clustering library:
+ * bulk-synchronous C4 and ClusterWild! (Pan, Papailiopoulos, Oymak, Recht,
+ * Ramchandran, Jordan, "Parallel Correlation Clustering on Big Graphs",
+ * arXiv 1507.05086).
+ *
+ * Problem (Section 2, "Correlation Clustering"): a complete graph on n
+ * vertices whose pairs are either positive (similar) or negative.  Only the
+ * positive edges are passed in; every other pair is negative.  A clustering
+ * is scored by its disagreements: positive edges cut between clusters plus
+ * negative pairs placed inside a cluster.
+ *
+ * Conventions shared by every call:
+ *  - The positive graph is symmetric CSR: offsets int64[n+1], cols
+ *    int32[offsets[n]]; row v lists the positive neighbours N(v) in strictly
+ *    ascending order; no self-loops, no duplicates, every edge in both rows.
+ *    n < 2^31 and offsets[n] < 2^33.
+ *  - The order pi is passed as `order`, order[k] = the vertex of rank k (the
+ *    position-to-vertex reading of pi in Algorithm 1); it must be a
+ *    permutation of 0..n-1.
+ *  - Labels are int32[n]: labels[v] = the vertex id of v's cluster center
+ *    (the paper's clusterID holds the center's rank pi(center); the id is
+ *    the same information, one-to-one).
+ *  - `stream` is a hipStream_t passed as an opaque pointer (NULL = the null
+ *    stream).  Work is queued on it and every call returns after that work
+ *    has finished, so the status it returns covers the GPU work.
+ *  - Pointers are host pointers unless a flag says they are device pointers.
+ *    Caller-owned buffers are only read or written during the call.
+ *  - No call throws; each returns a cc_status.  On failure the outputs are
+ *    left untouched and cc_last_error() describes the failure.
+ *  - Calls that use the same cc_graph must not overlap (they share its
+ *    device workspace); different graphs may be used from different threads.
+ */
+#ifndef CC_H_
+#define CC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cc_graph cc_graph; /* opaque: device CSR + run workspace */
+
+typedef enum cc_status {
+  CC_OK = 0,
+  CC_ERR_INVALID_ARG = 1,     /* bad pointer, size, flag or eps */
+  CC_ERR_NOT_SYMMETRIC = 2,   /* edge (u,v) without (v,u) (CC_VALIDATE) */
+  CC_ERR_SELF_LOOP = 3,       /* edge (v,v) (CC_VALIDATE) */
+  CC_ERR_DUPLICATE_EDGE = 4,  /* repeated or unsorted entry in a row (CC_VALIDATE) */
+  CC_ERR_NOT_PERMUTATION = 5, /* order is not a permutation of 0..n-1 */
+  CC_ERR_OUT_OF_MEMORY = 6,   /* device or host allocation failed */
+  CC_ERR_DEVICE = 7,          /* a HIP call failed */
+  CC_ERR_NO_PROGRESS = 8,     /* round loop exceeded n+1 rounds or a bounded wait expired */
+  CC_ERR_POLICY = 9,          /* invalid epsilon-policy parameters or schedule */
+  CC_ERR_OUT_OF_RANGE = 10    /* a column index outside 0..n-1 (always checked) */
+} cc_status;
+
+enum cc_flags {
+  CC_VALIDATE = 1u,         /* graph: check symmetry, self-loops, duplicates, sort order */
+  CC_INPUT_ON_DEVICE = 2u,  /* offsets/cols (graph) or order (run) are device pointers */
+  CC_BORROW = 4u,           /* graph: keep the caller's device offsets/cols, no copy */
+  CC_OUTPUT_ON_DEVICE = 8u  /* labels (run) are a device pointer */
+};
+
+/* One record per round of the bulk-synchronous loop (Algorithm 2). */
+typedef struct cc_round_record {
+  int64_t n_i;       /* vertices unclustered when the round starts */
+  int64_t delta_i;   /* maximum remaining positive degree when it starts */
+  int64_t b_i;       /* active-set size used */
+  int64_t r_i;       /* rank (position in pi) of the last active vertex */
+  int64_t centers;   /* cluster centers created */
+  int64_t claimed;   /* non-center vertices clustered */
+  int64_t conflicts; /* active vertices with an earlier-ranked active neighbour */
+  double eps_used;   /* epsilon that produced b_i (b_i as given for a schedule) */
+  int64_t t_ns;      /* device time of the round, nanoseconds */
+} cc_round_record;
+
+/* Optional statistics of a run (pass NULL to skip). */
+typedef struct cc_run_stats {
+  int64_t rounds;        /* out: rounds executed */
+  int64_t scanned_elect; /* out: adjacency entries read by the C4 election */
+  int64_t scanned_claim; /* out: adjacency entries read by claims */
+  int64_t scanned_peel;  /* out: adjacency entries read by peeling */
+  int64_t blocked;       /* out: sum of conflicts over rounds */
+  int32_t policy_fallback; /* out: 1 if the learned policy fell back to the fixed rule */
+  int32_t truncated;       /* out: 1 if more rounds ran than trace_capacity */
+  cc_round_record *trace;  /* in: host buffer of trace_capacity records, or NULL */
+  int64_t trace_capacity;  /* in */
+} cc_run_stats;
+
+/*
+ * Upload (or borrow) a positive-edge graph.
+ *   num_graphs  1 for one graph; >1 for a batch of independent graphs whose
+ *               rows are stacked: vtx_ptr[num_graphs+1] (host) gives each
+ *               graph's first row, offsets index the shared cols array, and
+ *               cols hold LOCAL ids (0..n_g-1) of the same graph.
+ *               vtx_ptr may be NULL when num_graphs == 1.
+ *   n_total     total rows.
+ *   offsets, cols  CSR as described above; host pointers, or device
+ *               pointers with CC_INPUT_ON_DEVICE (copied) or CC_BORROW (kept;
+ *               the caller keeps them alive and unchanged until destroy).
+ *   flags       CC_VALIDATE / CC_INPUT_ON_DEVICE / CC_BORROW.
+ *   out         receives the handle.
+ * Column ranges are always checked (CC_ERR_OUT_OF_RANGE); CC_VALIDATE adds
+ * the symmetry, self-loop and duplicate/sort checks.
+ */
+int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_total,
+                          const int64_t *offsets, const int32_t *cols, uint32_t flags,
+                          void *stream, cc_graph **out);
+
+/* Release the handle and its device memory (borrowed CSR is not freed). */
+int32_t cc_graph_destroy(cc_graph *g);
+
+/* Rows and stored entries of a handle (either pointer may be NULL). */
+int32_t cc_graph_info(const cc_graph *g, int64_t *n_total, int64_t *nnz, int32_t *num_graphs);
+
+/*
+ * C4 (Algorithm 2, concurrency-control branch): rounds of
+ *   Delta_i = max remaining degree;  A = next B_i = ceil(eps n_i / Delta_i)
+ *   unclustered vertices of pi;  an active vertex becomes a center iff no
+ *   earlier-ranked active neighbour is one (concurrency rule 1);  every
+ *   other unclustered neighbour of a center joins the adjacent center of
+ *   lowest rank (rule 2);  clustered vertices are peeled.
+ * Its labels equal serial KwikCluster's under the same pi (Section 3,
+ * "C4 is serializable"), whatever the schedule.
+ *   order   int32[n_total]: pi (per graph, local ids, for a batch).
+ *   eps     0 < eps <= 1000, used in millionths: B_i = ceil(round(eps*1e6) *
+ *           n_i / (1e6 * Delta_i)), kept in [1, n_i]; B_i = n_i when
+ *           Delta_i = 0.  The process-wide policy (cc_set_eps_policy) may
+ *           replace this rule.
+ *   labels  int32[n_total] out (center ids; local ids for a batch).
+ *   stats   optional.
+ *   flags   CC_INPUT_ON_DEVICE (order), CC_OUTPUT_ON_DEVICE (labels).
+ */
+int32_t cc_c4(const cc_graph *g, const int32_t *order, double eps, int32_t *labels,
+              cc_run_stats *stats, uint32_t flags, void *stream);
+
+/*
+ * ClusterWild! (Algorithm 2, coordination-free branch): the same rounds,
+ * but every active vertex is a center (rule 1 is ignored) and centers claim
+ * only their non-active unclustered neighbours (createCluster's
+ * Gamma(v) \ A), the lowest-rank center winning.  Same arguments as cc_c4.
+ */
+int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double eps, int32_t *labels,
+                       cc_run_stats *stats, uint32_t flags, void *stream);
+
+/*
+ * Disagreements of a clustering (the objective of Section 2):
+ *   cost = sum over clusters of C(size, 2) + m - 2 * m_in,
+ * with m positive edges and m_in of them inside clusters.
+ *   labels  int32[n_total], each in 0..n_g-1 (any cluster ids, not only
+ *           centers); device pointer with CC_INPUT_ON_DEVICE.
+ *   cost    int64[num_graphs] host output, one value per graph.
+ */
+int32_t cc_cost(const cc_graph *g, const int32_t *labels, int64_t *cost, uint32_t flags,
+                void *stream);
+
+/* Epsilon policies for the active-set size of each round. */
+enum cc_eps_policy_kind {
+  CC_EPS_FIXED = 0,   /* the paper's rule with the per-call eps (default) */
+  CC_EPS_LEARNED = 1, /* params: 6->64->1 MLP, CC_MLP_PARAMS floats (see below) */
+  CC_EPS_TRACE = 2    /* params: int64 B_i schedule (each >= 1); rounds past its end use the fixed rule */
+};
+
+/*
+ * Set the process-wide policy (not thread-safe; call between runs).
+ * LEARNED: params = float32[CC_MLP_PARAMS] laid out W1[64][6] row-major, b1[64],
+ *   w2[64], b2; features per round x = [ln n_i, ln max(Delta_i,1),
+ *   conflicts/B, claimed/n, eps, i] of the previous round (zeros and the
+ *   per-call eps in round 0); eps_i = clamp(exp(w2 . relu(W1 x + b1) + b2),
+ *   eps_min, eps_max); a non-finite output falls back to the fixed rule.
+ * TRACE: params = int64[nbytes/8] schedule of B_i.
+ * FIXED: params ignored.
+ */
+int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes, double eps_min,
+                          double eps_max);
+
+#define CC_MLP_IN 6
+#define CC_MLP_HIDDEN 64
+#define CC_MLP_PARAMS (CC_MLP_HIDDEN * CC_MLP_IN + CC_MLP_HIDDEN + CC_MLP_HIDDEN + 1)
+
+/* Text of the calling thread's last failure ("" if none). */
+const char *cc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CC_H_ */

@@ -1,0 +1,168 @@
+"""CPU oracle for C4 / ClusterWild! (arXiv 1507.05086).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py`` -- never by the GPU library in
+``paper_1507_05086_amd``.  The two share no code; both read the arrays that
+``graphgen`` writes.
+
+``cc_oracle.c`` holds the plain serial algorithms (KwikCluster, the BSP
+simulator of C4 and ClusterWild!, the objective counted three ways, and the
+any-size KwikCluster checker); ``mlp.py`` holds the float64 reference of the
+small epsilon-policy network.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libcc_oracle.so")
+_lib = None
+
+C4, CW = 0, 1
+TRACE_FIELDS = ("n_i", "delta_i", "b_i", "r_i", "centers", "claimed", "conflicts")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle (serial, portable -O2) into libcc_oracle.so."""
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Round(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in TRACE_FIELDS]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.orc_kwikcluster.argtypes = [i64, vp, vp, vp, vp]
+    lib.orc_kwikcluster.restype = i32
+    lib.orc_bsp.argtypes = [i32, i64, vp, vp, vp, i64, vp, i64, vp, vp, i64]
+    lib.orc_bsp.restype = i64
+    lib.orc_quantize_eps.argtypes = [ctypes.c_double]
+    lib.orc_quantize_eps.restype = i64
+    lib.orc_cost.argtypes = [i64, vp, vp, vp]
+    lib.orc_cost.restype = i64
+    lib.orc_cost_pairs.argtypes = [i64, vp, vp, vp]
+    lib.orc_cost_pairs.restype = i64
+    lib.orc_kc_stepwise_cost.argtypes = [i64, vp, vp, vp]
+    lib.orc_kc_stepwise_cost.restype = i64
+    lib.orc_check_kc.argtypes = [i64, vp, vp, vp, vp, vp]
+    lib.orc_check_kc.restype = i64
+    _lib = lib
+    return lib
+
+
+def _c(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+@dataclass
+class BSPResult:
+    labels: np.ndarray
+    rounds: int
+    trace: np.ndarray  # structured array with TRACE_FIELDS
+
+    def trace_dict(self, i: int) -> dict:
+        return {f: int(self.trace[f][i]) for f in TRACE_FIELDS}
+
+
+def kwikcluster(off, col, order) -> np.ndarray:
+    """KwikCluster with order pi (Algorithm 1): labels = center vertex ids."""
+    off, po = _c(off, np.int64)
+    col, pc = _c(col, np.int32)
+    order, pr = _c(order, np.int32)
+    n = len(off) - 1
+    labels = np.empty(n, dtype=np.int32)
+    rc = _load().orc_kwikcluster(n, po, pc, pr, labels.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_kwikcluster failed ({rc})")
+    return labels
+
+
+def quantize_eps(eps: float) -> int:
+    return int(_load().orc_quantize_eps(eps))
+
+
+def bsp(algo: int, off, col, order, eps: float = 0.5, sched=None, trace_cap: int = 1 << 16) -> BSPResult:
+    """Serial simulation of the BSP round loop (Algorithm 2), C4 or ClusterWild!."""
+    off, po = _c(off, np.int64)
+    col, pc = _c(col, np.int32)
+    order, pr = _c(order, np.int32)
+    n = len(off) - 1
+    labels = np.empty(n, dtype=np.int32)
+    trace = np.zeros(trace_cap, dtype=[(f, np.int64) for f in TRACE_FIELDS])
+    if sched is None:
+        sp, slen = None, 0
+    else:
+        sched, sp = _c(sched, np.int64)
+        slen = len(sched)
+    rounds = _load().orc_bsp(algo, n, po, pc, pr, quantize_eps(eps), sp, slen,
+                             labels.ctypes.data, trace.ctypes.data, trace_cap)
+    if rounds < 0:
+        raise ValueError(f"orc_bsp failed ({rounds})")
+    return BSPResult(labels=labels, rounds=int(rounds), trace=trace[:min(rounds, trace_cap)])
+
+
+def c4(off, col, order, eps=0.5, sched=None, trace_cap=1 << 16) -> BSPResult:
+    return bsp(C4, off, col, order, eps, sched, trace_cap)
+
+
+def clusterwild(off, col, order, eps=0.5, sched=None, trace_cap=1 << 16) -> BSPResult:
+    return bsp(CW, off, col, order, eps, sched, trace_cap)
+
+
+def cost(off, col, labels) -> int:
+    """Disagreements (objective of Section 2) in closed form."""
+    off, po = _c(off, np.int64)
+    col, pc = _c(col, np.int32)
+    labels, pl = _c(labels, np.int32)
+    r = _load().orc_cost(len(off) - 1, po, pc, pl)
+    if r < 0:
+        raise ValueError("labels out of range")
+    return int(r)
+
+
+def cost_pairs(off, col, labels) -> int:
+    """Disagreements counted pair by pair (O(n^2); small graphs)."""
+    off, po = _c(off, np.int64)
+    col, pc = _c(col, np.int32)
+    labels, pl = _c(labels, np.int32)
+    return int(_load().orc_cost_pairs(len(off) - 1, po, pc, pl))
+
+
+def kc_stepwise_cost(off, col, order) -> int:
+    """KwikCluster's cost summed per peeling step (bad-triangle lemma)."""
+    off, po = _c(off, np.int64)
+    col, pc = _c(col, np.int32)
+    order, pr = _c(order, np.int32)
+    return int(_load().orc_kc_stepwise_cost(len(off) - 1, po, pc, pr))
+
+
+def check_kc(off, col, order, labels):
+    """(violations, first_bad_vertex): 0 violations iff labels == KwikCluster(G, pi)."""
+    off, po = _c(off, np.int64)
+    col, pc = _c(col, np.int32)
+    order, pr = _c(order, np.int32)
+    labels, pl = _c(labels, np.int32)
+    first = ctypes.c_int64(-1)
+    r = _load().orc_check_kc(len(off) - 1, po, pc, pr, pl, ctypes.byref(first))
+    if r < 0:
+        raise ValueError(f"orc_check_kc failed ({r})")
+    return int(r), int(first.value)
