@@ -1,0 +1,150 @@
+#!/usr/bin/env python3
+"""Throughput of the C4 + ClusterWild! round loop on one MI355X.
+
+A step is one cc_c4 call plus one cc_clusterwild call (fixed eps rule) on the
+same resident graph and order: every step of the hot path (delta, active-set
+selection, election, claims, peeling, labels) runs once per algorithm.
+`value` is positive edges clustered per second over the step:
+2 * m / step_time.  Inputs (CSR, order, output buffers) are in HBM before the
+timed region starts.
+
+Default workload: R-MAT scale 26, edge factor 16, (a,b,c,d) = (0.57, 0.19,
+0.19, 0.05), symmetrised and deduplicated (~1.05e9 undirected positive
+edges), seeded order, eps = 0.5.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_graph(name):
+    import graphgen
+    return graphgen.workload(name)
+
+
+def algorithmic_bytes(st, n):
+    """Bytes the method itself must move in one call (see the design notes):
+    8 B per adjacency item scanned (4 B column + 4 B neighbour word) in the
+    election, claim and peel passes, 8 B per atomic read-modify-write, and
+    32 B per vertex (offsets, order, rank, initial state, final label)."""
+    return 8 * (st.scanned_elect + st.scanned_claim + st.scanned_peel) + 8 * st.atomics + 32 * n
+
+
+def cpu_baseline(sample):
+    """The oracle, as it stands, on a bounded sample of the same graph family."""
+    import graphgen
+    import oracle
+    g = graphgen.workload(sample)
+    order = graphgen.permutation(g.n, 31)
+    t0 = time.perf_counter()
+    oracle.c4(g.off, g.col, order, 0.5)
+    t1 = time.perf_counter()
+    oracle.clusterwild(g.off, g.col, order, 0.5)
+    t2 = time.perf_counter()
+    return {"value": 2 * g.m / (t2 - t0), "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample} (n={g.n}, m={g.m}), C4 + ClusterWild! BSP oracle, eps=0.5, one thread: "
+                      f"C4 {t1 - t0:.2f} s, ClusterWild! {t2 - t1:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat26")
+    ap.add_argument("--eps", type=float, default=0.5)
+    ap.add_argument("--seed", type=int, default=31)
+    ap.add_argument("--cpu-sample", default="rmat23")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the round loop runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import graphgen
+    import paper_1507_05086_amd as cc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    g = make_graph(args.workload)
+    log(f"graph {args.workload}: n={g.n} m={g.m} max_deg={int(g.degrees().max())} "
+        f"generated in {time.perf_counter() - t:.1f} s")
+    off = torch.from_numpy(np.ascontiguousarray(g.off)).to(dev)
+    col = torch.from_numpy(np.ascontiguousarray(g.col)).to(dev)
+    n, m = g.n, g.m
+    del g
+    gh = cc.cc_graph_from_csr(off, col, borrow=True)
+    order = torch.from_numpy(graphgen.permutation(n, args.seed)).to(dev)
+    lab_c4 = torch.empty(n, dtype=torch.int32, device=dev)
+    lab_cw = torch.empty(n, dtype=torch.int32, device=dev)
+    cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+
+    def step():
+        _, s4 = cc.cc_c4(gh, order, args.eps, labels=lab_c4)
+        _, sw = cc.cc_clusterwild(gh, order, args.eps, labels=lab_cw)
+        return s4, sw
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        stats.append(step())
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    value = 2 * m / (ms_per_step / 1e3)
+
+    c4 = [s[0] for s in stats]
+    cw = [s[1] for s in stats]
+
+    def summary(runs):
+        loop = float(np.mean([r.loop_ms for r in runs]))
+        nbytes = algorithmic_bytes(runs[-1], n)
+        return {"loop_ms": round(loop, 3), "rounds": runs[-1].rounds, "edges_per_s": m / (loop / 1e3),
+                "alg_bytes": nbytes, "achieved_gbs": nbytes / (loop / 1e3) / 1e9,
+                "atomics": runs[-1].atomics,
+                "scanned": runs[-1].scanned_elect + runs[-1].scanned_claim + runs[-1].scanned_peel}
+
+    s4, sw = summary(c4), summary(cw)
+    dom = s4 if s4["loop_ms"] >= sw["loop_ms"] else sw
+    roof = {"bound": "hbm", "achieved": round(dom["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "round loop of " + ("cc_c4" if dom is s4 else "cc_clusterwild")}
+    line = {
+        "metric": "edges/sec (C4 + ClusterWild! round loop, fixed eps)",
+        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "eps": args.eps, "order_seed": args.seed,
+                   "step": "cc_c4 + cc_clusterwild"},
+        "c4": s4, "clusterwild": sw,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,17 +105,36 @@ class Graph:
         return np.diff(self.off)
 
 
+class _Owner:
+    """Frees a generator-owned CSR once no array views it any more."""
+
+    def __init__(self, ptr):
+        self._ptr = ptr
+
+    def __del__(self):
+        if self._ptr is not None and _lib is not None:
+            _lib.gg_free(self._ptr)
+            self._ptr = None
+
+
+class _View:
+    def __init__(self, addr: int, count: int, typestr: str, owner: _Owner):
+        self.__array_interface__ = {"data": (addr, False), "shape": (count,),
+                                    "typestr": typestr, "version": 3}
+        self._owner = owner
+
+
 def _take(ptr) -> Graph:
-    lib = _load()
+    """Wraps the C buffers in NumPy arrays without copying them."""
     c = ptr.contents
     n, nnz = int(c.n), int(c.nnz)
-    off = np.ctypeslib.as_array(c.off, shape=(n + 1,)).copy()
-    col = (np.ctypeslib.as_array(c.col, shape=(nnz,)).copy() if nnz > 0
+    owner = _Owner(ptr)
+    off = np.asarray(_View(ctypes.addressof(c.off.contents), n + 1, "<i8", owner))
+    col = (np.asarray(_View(ctypes.addressof(c.col.contents), nnz, "<i4", owner)) if nnz > 0
            else np.zeros(0, dtype=np.int32))
     vp = None
     if c.vtx_ptr:
-        vp = np.ctypeslib.as_array(c.vtx_ptr, shape=(int(c.ngraphs) + 1,)).copy()
-    lib.gg_free(ptr)
+        vp = np.asarray(_View(ctypes.addressof(c.vtx_ptr.contents), int(c.ngraphs) + 1, "<i8", owner))
     return Graph(n=n, off=off, col=col, vtx_ptr=vp)
 
 

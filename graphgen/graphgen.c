@@ -149,9 +149,35 @@ void gg_free(gg_csr *g) {
   free(g);
 }
 
-static int gg_cmp_i32(const void *a, const void *b) {
-  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
-  return (x > y) - (x < y);
+/* Sorts a[0..len) ascending: insertion sort for short rows, else an LSD
+ * radix sort on `bits`-bit keys (non-negative values) using tmp[len]. */
+static void gg_sort_row(int32_t *a, int64_t len, int bits, int32_t *tmp) {
+  if (len <= 48) {
+    for (int64_t i = 1; i < len; i++) {
+      int32_t x = a[i];
+      int64_t j = i - 1;
+      while (j >= 0 && a[j] > x) {
+        a[j + 1] = a[j];
+        j--;
+      }
+      a[j + 1] = x;
+    }
+    return;
+  }
+  const int passes = (bits + 10) / 11;
+  int32_t *src = a, *dst = tmp;
+  for (int p = 0; p < passes; p++) {
+    const int shift = 11 * p;
+    int64_t cnt[2049];
+    memset(cnt, 0, sizeof(cnt));
+    for (int64_t i = 0; i < len; i++) cnt[(((uint32_t)src[i] >> shift) & 2047u) + 1]++;
+    for (int d = 0; d < 2048; d++) cnt[d + 1] += cnt[d];
+    for (int64_t i = 0; i < len; i++) dst[cnt[((uint32_t)src[i] >> shift) & 2047u]++] = src[i];
+    int32_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != a) memcpy(a, src, sizeof(int32_t) * (size_t)len);
 }
 
 /* Sort every row, drop duplicate entries, then compact rows to the left.
@@ -159,15 +185,25 @@ static int gg_cmp_i32(const void *a, const void *b) {
 static void gg_sort_dedup_compact(gg_csr *g) {
   const int64_t n = g->n;
   int64_t *newdeg = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-#pragma omp parallel for schedule(dynamic, 4096)
-  for (int64_t v = 0; v < n; v++) {
-    int32_t *row = g->col + g->off[v];
-    int64_t len = g->off[v + 1] - g->off[v];
-    if (len > 1) qsort(row, (size_t)len, sizeof(int32_t), gg_cmp_i32);
-    int64_t k = 0;
-    for (int64_t i = 0; i < len; i++)
-      if (k == 0 || row[i] != row[k - 1]) row[k++] = row[i];
-    newdeg[v] = k;
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < n) bits++;
+  int64_t maxlen = 0;
+  for (int64_t v = 0; v < n; v++)
+    if (g->off[v + 1] - g->off[v] > maxlen) maxlen = g->off[v + 1] - g->off[v];
+#pragma omp parallel
+  {
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxlen > 0 ? maxlen : 1));
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t v = 0; v < n; v++) {
+      int32_t *row = g->col + g->off[v];
+      int64_t len = g->off[v + 1] - g->off[v];
+      gg_sort_row(row, len, bits, tmp);
+      int64_t k = 0;
+      for (int64_t i = 0; i < len; i++)
+        if (k == 0 || row[i] != row[k - 1]) row[k++] = row[i];
+      newdeg[v] = k;
+    }
+    free(tmp);
   }
   /* rows only move left, so a forward serial pass can compact in place */
   int64_t pos = 0;
@@ -382,11 +418,9 @@ static inline void gg_rmat_sample(uint64_t key, uint64_t e, int scale, uint32_t 
       int level = 2 * k + h;
       if (level >= scale) break;
       uint32_t r = (uint32_t)(h ? (x >> 32) : x);
-      uint32_t bu, bv;
-      if (r < ta) { bu = 0; bv = 0; }
-      else if (r < tab) { bu = 0; bv = 1; }
-      else if (r < tabc) { bu = 1; bv = 0; }
-      else { bu = 1; bv = 1; }
+      /* quadrant 0..3 = a, b, c, d; row bit = q >> 1, column bit = q & 1 */
+      const uint32_t q = (uint32_t)(r >= ta) + (uint32_t)(r >= tab) + (uint32_t)(r >= tabc);
+      const uint32_t bu = q >> 1, bv = q & 1u;
       u = (u << 1) | bu;
       v = (v << 1) | bv;
     }
@@ -402,41 +436,100 @@ static inline uint32_t gg_prob32(double p) {
   return (uint32_t)t;
 }
 
-/* R-MAT with 2^scale vertices and edge_factor * 2^scale samples. */
+/* R-MAT with 2^scale vertices and edge_factor * 2^scale samples.
+ * Two passes over the counter-based sample stream: count row lengths, then
+ * place entries.  Each thread owns a fixed slice of the samples and private
+ * per-row counters (no atomics), and samples are handled in blocks so the
+ * cache misses of one block overlap. */
+#define GG_BLK 64
 gg_csr *gg_rmat(int scale, int64_t edge_factor, double a, double b, double c, uint64_t seed) {
   const int64_t n = (int64_t)1 << scale;
   const uint64_t samples = (uint64_t)edge_factor << scale;
   const uint32_t ta = gg_prob32(a), tab = gg_prob32(a + b), tabc = gg_prob32(a + b + c);
   const uint64_t key = gg_mix64(seed * GG_GOLDEN + 0x2545F4914F6CDD1DULL);
   int32_t *relabel = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!relabel) return NULL;
   gg_permutation(seed ^ 0x9FB21C651E98DF25ULL, n, relabel);
+  int nt = 1;
+#ifdef _OPENMP
+  nt = omp_get_max_threads();
+#endif
+  /* cnt[t*n + x]: entries of row x produced by thread t; later its cursor */
+  int32_t *cnt = (int32_t *)calloc((size_t)nt * (size_t)n, sizeof(int32_t));
   gg_csr *g = gg_alloc(n);
-  int64_t *deg = g->off + 1;
-#pragma omp parallel for schedule(static, 65536)
-  for (uint64_t e = 0; e < samples; e++) {
-    uint32_t u, v;
-    gg_rmat_sample(key, e, scale, ta, tab, tabc, &u, &v);
-    if (u == v) continue;
-    __atomic_fetch_add(&deg[relabel[u]], 1, __ATOMIC_RELAXED);
-    __atomic_fetch_add(&deg[relabel[v]], 1, __ATOMIC_RELAXED);
-  }
-  if (!gg_offsets_from_counts(g)) {
-    gg_free(g);
+  if (!cnt || !g || !g->off) {
     free(relabel);
+    free(cnt);
+    gg_free(g);
     return NULL;
   }
-  int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-  memcpy(cur, g->off, sizeof(int64_t) * (size_t)n);
-#pragma omp parallel for schedule(static, 65536)
-  for (uint64_t e = 0; e < samples; e++) {
-    uint32_t u, v;
-    gg_rmat_sample(key, e, scale, ta, tab, tabc, &u, &v);
-    if (u == v) continue;
-    int32_t x = relabel[u], y = relabel[v];
-    g->col[__atomic_fetch_add(&cur[x], 1, __ATOMIC_RELAXED)] = y;
-    g->col[__atomic_fetch_add(&cur[y], 1, __ATOMIC_RELAXED)] = x;
+  const uint64_t per = (samples + (uint64_t)nt - 1) / (uint64_t)nt;
+#pragma omp parallel num_threads(nt)
+  {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    int32_t *mine = cnt + (size_t)t * (size_t)n;
+    const uint64_t e0 = (uint64_t)t * per, e1 = (e0 + per < samples) ? e0 + per : samples;
+    uint32_t bu[GG_BLK], bv[GG_BLK];
+    int32_t bx[GG_BLK], by[GG_BLK];
+    for (uint64_t eb = e0; eb < e1; eb += GG_BLK) {
+      const int m = (int)((e1 - eb) < GG_BLK ? (e1 - eb) : GG_BLK);
+      for (int i = 0; i < m; i++) gg_rmat_sample(key, eb + (uint64_t)i, scale, ta, tab, tabc, &bu[i], &bv[i]);
+      for (int i = 0; i < m; i++) {
+        bx[i] = relabel[bu[i]];
+        by[i] = relabel[bv[i]];
+      }
+      for (int i = 0; i < m; i++)
+        if (bu[i] != bv[i]) {
+          mine[bx[i]]++;
+          mine[by[i]]++;
+        }
+    }
   }
-  free(cur);
+  /* row lengths, offsets, and per-thread cursors (exclusive within a row) */
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < n; x++) {
+    int64_t acc = 0;
+    for (int t = 0; t < nt; t++) {
+      int32_t c0 = cnt[(size_t)t * (size_t)n + (size_t)x];
+      cnt[(size_t)t * (size_t)n + (size_t)x] = (int32_t)acc;
+      acc += c0;
+    }
+    g->off[x + 1] = acc;
+  }
+  if (!gg_offsets_from_counts(g)) {
+    free(relabel);
+    free(cnt);
+    gg_free(g);
+    return NULL;
+  }
+#pragma omp parallel num_threads(nt)
+  {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    int32_t *mine = cnt + (size_t)t * (size_t)n;
+    const uint64_t e0 = (uint64_t)t * per, e1 = (e0 + per < samples) ? e0 + per : samples;
+    uint32_t bu[GG_BLK], bv[GG_BLK];
+    int32_t bx[GG_BLK], by[GG_BLK];
+    for (uint64_t eb = e0; eb < e1; eb += GG_BLK) {
+      const int m = (int)((e1 - eb) < GG_BLK ? (e1 - eb) : GG_BLK);
+      for (int i = 0; i < m; i++) gg_rmat_sample(key, eb + (uint64_t)i, scale, ta, tab, tabc, &bu[i], &bv[i]);
+      for (int i = 0; i < m; i++) {
+        bx[i] = relabel[bu[i]];
+        by[i] = relabel[bv[i]];
+      }
+      for (int i = 0; i < m; i++)
+        if (bu[i] != bv[i]) {
+          g->col[g->off[bx[i]] + mine[bx[i]]++] = by[i];
+          g->col[g->off[by[i]] + mine[by[i]]++] = bx[i];
+        }
+    }
+  }
+  free(cnt);
   free(relabel);
   gg_sort_dedup_compact(g);
   return g;

@@ -41,6 +41,12 @@
 extern "C" {
 #endif
 
+#if defined(__GNUC__) || defined(__clang__)
+#define CC_API __attribute__((visibility("default")))
+#else
+#define CC_API
+#endif
+
 typedef struct cc_graph cc_graph; /* opaque: device CSR + run workspace */
 
 typedef enum cc_status {
@@ -80,10 +86,12 @@ typedef struct cc_round_record {
 /* Optional statistics of a run (pass NULL to skip). */
 typedef struct cc_run_stats {
   int64_t rounds;        /* out: rounds executed */
-  int64_t scanned_elect; /* out: adjacency entries read by the C4 election */
-  int64_t scanned_claim; /* out: adjacency entries read by claims */
-  int64_t scanned_peel;  /* out: adjacency entries read by peeling */
+  int64_t scanned_elect; /* out: adjacency entries (+1 per isolated row) read by the C4 election */
+  int64_t scanned_claim; /* out: adjacency entries (+1 per isolated row) read by claims */
+  int64_t scanned_peel;  /* out: adjacency entries (+1 per isolated row) read by peeling */
   int64_t blocked;       /* out: sum of conflicts over rounds */
+  int64_t atomics;       /* out: atomic read-modify-writes (claims and degree decrements) */
+  double loop_ms;        /* out: device time of the round loop (HIP events on `stream`) */
   int32_t policy_fallback; /* out: 1 if the learned policy fell back to the fixed rule */
   int32_t truncated;       /* out: 1 if more rounds ran than trace_capacity */
   cc_round_record *trace;  /* in: host buffer of trace_capacity records, or NULL */
@@ -106,15 +114,15 @@ typedef struct cc_run_stats {
  * Column ranges are always checked (CC_ERR_OUT_OF_RANGE); CC_VALIDATE adds
  * the symmetry, self-loop and duplicate/sort checks.
  */
-int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_total,
+CC_API int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_total,
                           const int64_t *offsets, const int32_t *cols, uint32_t flags,
                           void *stream, cc_graph **out);
 
 /* Release the handle and its device memory (borrowed CSR is not freed). */
-int32_t cc_graph_destroy(cc_graph *g);
+CC_API int32_t cc_graph_destroy(cc_graph *g);
 
 /* Rows and stored entries of a handle (either pointer may be NULL). */
-int32_t cc_graph_info(const cc_graph *g, int64_t *n_total, int64_t *nnz, int32_t *num_graphs);
+CC_API int32_t cc_graph_info(const cc_graph *g, int64_t *n_total, int64_t *nnz, int32_t *num_graphs);
 
 /*
  * C4 (Algorithm 2, concurrency-control branch): rounds of
@@ -134,7 +142,7 @@ int32_t cc_graph_info(const cc_graph *g, int64_t *n_total, int64_t *nnz, int32_t
  *   stats   optional.
  *   flags   CC_INPUT_ON_DEVICE (order), CC_OUTPUT_ON_DEVICE (labels).
  */
-int32_t cc_c4(const cc_graph *g, const int32_t *order, double eps, int32_t *labels,
+CC_API int32_t cc_c4(const cc_graph *g, const int32_t *order, double eps, int32_t *labels,
               cc_run_stats *stats, uint32_t flags, void *stream);
 
 /*
@@ -143,7 +151,7 @@ int32_t cc_c4(const cc_graph *g, const int32_t *order, double eps, int32_t *labe
  * only their non-active unclustered neighbours (createCluster's
  * Gamma(v) \ A), the lowest-rank center winning.  Same arguments as cc_c4.
  */
-int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double eps, int32_t *labels,
+CC_API int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double eps, int32_t *labels,
                        cc_run_stats *stats, uint32_t flags, void *stream);
 
 /*
@@ -154,7 +162,7 @@ int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double eps, int3
  *           centers); device pointer with CC_INPUT_ON_DEVICE.
  *   cost    int64[num_graphs] host output, one value per graph.
  */
-int32_t cc_cost(const cc_graph *g, const int32_t *labels, int64_t *cost, uint32_t flags,
+CC_API int32_t cc_cost(const cc_graph *g, const int32_t *labels, int64_t *cost, uint32_t flags,
                 void *stream);
 
 /* Epsilon policies for the active-set size of each round. */
@@ -174,7 +182,7 @@ enum cc_eps_policy_kind {
  * TRACE: params = int64[nbytes/8] schedule of B_i.
  * FIXED: params ignored.
  */
-int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes, double eps_min,
+CC_API int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes, double eps_min,
                           double eps_max);
 
 #define CC_MLP_IN 6
@@ -182,7 +190,7 @@ int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes, doubl
 #define CC_MLP_PARAMS (CC_MLP_HIDDEN * CC_MLP_IN + CC_MLP_HIDDEN + CC_MLP_HIDDEN + 1)
 
 /* Text of the calling thread's last failure ("" if none). */
-const char *cc_last_error(void);
+CC_API const char *cc_last_error(void);
 
 #ifdef __cplusplus
 }

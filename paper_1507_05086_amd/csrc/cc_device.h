@@ -1,0 +1,233 @@
+// cc_device.h -- device-side data layout and helpers of the C4 / ClusterWild!
+// round loop (arXiv 1507.05086, Algorithm 2) on gfx950.
+//
+// Memory layout of a run (all in HBM, sized for one graph of n vertices and
+// nnz stored adjacency entries):
+//   rank   int32[n]  position of each vertex in pi (rank = order^-1)
+//   lab    int32[n]  clusterID: rank of the vertex's center, INF while unclustered
+//   resdeg int32[n]  remaining positive degree (unclustered neighbours)
+//   state  uint8[n]  UNCL / ACTIVE / CENTER / NONCENTER / CLUST (67 MB at 2^26
+//                    vertices: small enough to stay in the 256 MB Infinity Cache)
+//   flag   uint8[n]  per-round scratch mark (blocked / waiting / conflict)
+//   three work lists (active set, centers, newly clustered), each a vertex
+//   array plus the exclusive prefix of the row weights max(deg, 1), so that
+//   adjacency passes can hand out equal numbers of entries to every workgroup.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccd {
+
+constexpr int BS = 256;             // threads per workgroup (4 wave64s)
+constexpr int WAVES = BS / 64;
+constexpr int IPT = 4;              // adjacency items per thread per tile
+constexpr int TW = BS * IPT;        // adjacency items per tile
+constexpr int SIPT = 16;            // pi positions per thread in the active-set scan
+constexpr int TSEL = BS * SIPT;     // pi positions per scan tile
+constexpr int32_t INF = 0x7fffffff;
+
+enum : uint8_t { UNCL = 0, ACTIVE = 1, CENTER = 2, NONCENTER = 3, CLUST = 4 };
+enum : int { ALGO_C4 = 0, ALGO_CW = 1 };
+enum : int { POL_FIXED = 0, POL_LEARNED = 1, POL_TRACE = 2 };
+enum : int { ERR_NONE = 0, ERR_PERM = 5, ERR_NO_PROGRESS = 8, ERR_OVERFLOW = 11, ERR_LABEL = 12 };
+enum : int { FIN_CLASSIFY = 0, FIN_PEEL = 1, FIN_DELTA = 2, FIN_COST = 3, FIN_N = 8 };
+
+// A list is packed in one 64-bit counter: (total weight << 31) | count, so a
+// single atomic reserves both a slot range and its weight range, and the
+// stored weight offsets come out sorted in slot order.
+__host__ __device__ inline unsigned long long pk(int64_t work, int64_t cnt) {
+  return ((unsigned long long)work << 31) | (unsigned long long)cnt;
+}
+__host__ __device__ inline int64_t pk_cnt(unsigned long long p) { return (int64_t)(p & 0x7fffffffULL); }
+__host__ __device__ inline int64_t pk_work(unsigned long long p) { return (int64_t)(p >> 31); }
+
+struct RoundRec {  // mirrors cc_round_record
+  int64_t n_i, delta_i, b_i, r_i, centers, claimed, conflicts;
+  double eps_used;
+  int64_t t_ns;  // raw wall-clock ticks here; the host converts
+};
+
+struct Ctrl {
+  // carried across rounds
+  long long n_rem;         // unclustered vertices
+  long long delta;         // max remaining degree (current round)
+  long long cursor;        // first pi position not yet passed
+  long long b;             // active-set size of the current round
+  long long round;         // rounds finished
+  long long n_start;       // n_i of the current round
+  long long r_last;        // rank of the last active vertex
+  int done, error;
+  int has_round;           // the delta kernel closes a round (0 before round 0)
+  int fallback;            // learned policy fell back to the fixed rule
+  double eps_used;         // eps behind b
+  float feat_conf, feat_claim, feat_eps;  // previous-round features for the learned policy
+  int pad0;
+  long long t_start;       // wall clock at round start
+  // per round
+  unsigned long long a_pack, c_pack, n_pack;  // active / center / newly lists
+  unsigned int tile_counter;
+  int select_done;
+  unsigned int n_blocked, n_cedges;
+  int delta_next;
+  int pad1;
+  unsigned long long conflicts;
+  unsigned int fin[FIN_N];  // last-workgroup counters, one per kernel kind
+  // run totals
+  unsigned long long sum_elect, sum_claim, sum_peel, sum_blocked, sum_atomics;
+  long long trace_written;
+};
+
+struct Ws {
+  // graph
+  const int64_t *off;
+  const int32_t *col;
+  int64_t n;
+  // run input
+  const int32_t *order;
+  // per-vertex arrays
+  int32_t *rank, *lab, *resdeg;
+  uint8_t *state, *flag;
+  // lists
+  int32_t *alist, *clist, *nlist, *blist;
+  int64_t *awork, *cwork, *nwork;
+  int2 *cedge;
+  int64_t cedge_cap;
+  unsigned long long *tstat;
+  int64_t tstat_cap;
+  Ctrl *ctrl;
+  RoundRec *trace;
+  int64_t trace_cap;
+  // epsilon policy
+  int policy;
+  int algo;
+  int64_t eps_q;        // per-call eps in millionths
+  double eps;
+  const int64_t *sched; // TRACE: B_i schedule (device)
+  int64_t sched_len;
+  const float *mlp;     // LEARNED: 6-64-1 weights (device)
+  float eps_min, eps_max;
+};
+
+// ------------------------------------------------------------- atomics ----
+
+template <class T>
+__device__ inline T ld_acq(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline T ld_rlx(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline void st_rel(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline T add_rlx(T *p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void set_error(Ctrl *c, int code) { atomicCAS(&c->error, 0, code); }
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ inline int wave_id() { return (int)(threadIdx.x >> 6); }
+__device__ inline unsigned long long lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Inclusive wave64 scan of 64-bit values.
+__device__ inline int64_t wave_incl_scan(int64_t x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t y = __shfl_up(x, d, 64);
+    if (l >= d) x += y;
+  }
+  return x;
+}
+__device__ inline int64_t wave_sum(int64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+__device__ inline int wave_max(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, 64));
+  return x;
+}
+
+// Workgroup exclusive scan of 64-bit values; *total receives the sum.
+// Uses `sh` (WAVES+1 slots of shared memory); contains two barriers.
+__device__ inline int64_t wg_excl_scan(int64_t x, int64_t *total, int64_t *sh) {
+  const int64_t inc = wave_incl_scan(x);
+  if (lane_id() == 63) sh[wave_id()] = inc;
+  __syncthreads();
+  int64_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; w++) {
+    if (w < wave_id()) base += sh[w];
+    tot += sh[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - x;
+}
+
+// Append the calling lanes' vertices (pred true) to a packed list, one atomic
+// per wave.  weight = max(deg, 1) of the vertex.
+__device__ inline void wave_append(bool pred, int32_t v, int64_t weight, unsigned long long *packc,
+                                   int32_t *list, int64_t *work) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0) return;
+  const int64_t w = pred ? weight : 0;
+  const int64_t winc = wave_incl_scan(w);
+  const int64_t wtot = __shfl(winc, 63, 64);
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(packc, pk(wtot, __popcll(m)));
+  base = __shfl(base, leader, 64);
+  if (pred) {
+    const int64_t slot = pk_cnt(base) + __popcll(m & lanemask_lt());
+    list[slot] = v;
+    work[slot] = pk_work(base) + winc - w;
+  }
+}
+
+__device__ inline int64_t row_weight(const int64_t *off, int32_t v) {
+  const int64_t d = off[v + 1] - off[v];
+  return d > 0 ? d : 1;
+}
+
+// Largest i in [0, cnt) with work[i] <= s (work[0] = 0 <= s): a 64-ary search
+// by one wave, about log64(cnt) dependent loads.
+__device__ inline int64_t wave_find_entry(const int64_t *work, int64_t cnt, int64_t s) {
+  int64_t lo = 0, hi = cnt;
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t idx = lo + (int64_t)lane_id() * step;
+    const bool pred = idx < hi && work[idx] <= s;
+    const unsigned long long m = __ballot(pred);
+    const int k = __popcll(m);  // lanes 0..k-1 hold true (work is sorted)
+    lo = lo + (int64_t)(k - 1) * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
+// Last-workgroup detection: returns true in exactly one workgroup (the last
+// to arrive), after all others have made their writes visible.
+__device__ inline bool last_block(unsigned int *counter) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last != 0;
+}
+
+}  // namespace ccd

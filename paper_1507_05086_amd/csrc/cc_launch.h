@@ -1,0 +1,34 @@
+// cc_launch.h -- host-side entry points of the kernels (C++ linkage, internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "cc_device.h"
+
+namespace ccd {
+
+struct LaunchShape {
+  unsigned select_grid;  // workgroups of the active-set scan
+  unsigned edge_grid;    // workgroups of the edge-balanced passes
+  unsigned vertex_grid;  // workgroups of per-vertex list passes
+  unsigned scan_grid;    // cap on workgroups of the full-vertex delta scan
+};
+
+hipError_t launch_init(const Ws &w, hipStream_t s);
+hipError_t launch_round(const Ws &w, hipStream_t s, const LaunchShape &ls);
+hipError_t launch_finalize(const Ws &w, int32_t *labels, hipStream_t s);
+
+// Graph set-up: row-weight prefix wall[n+1] (the "all rows" list of the
+// edge-balanced walk), per-row graph ids (batches), column-range check and,
+// with validate, the symmetry / self-loop / duplicate checks.  *err receives
+// the smallest failing cc_status code (it must hold 0x7fffffff beforehand).
+hipError_t launch_graph_setup(const int64_t *off, const int32_t *col, int64_t n, const int64_t *vtx_ptr,
+                              int32_t num_graphs, int32_t *gid, int64_t *wall, int64_t *blocksum,
+                              int validate, int *err, hipStream_t s);
+
+// Disagreement cost per graph: acc[2g] = pairs inside clusters, acc[2g+1] =
+// same-label adjacency entries (2 m_in); size is scratch [n].
+hipError_t launch_cost(const int64_t *off, const int32_t *col, const int64_t *wall, int64_t n,
+                       const int64_t *vtx_ptr, const int32_t *gid, const int32_t *labels, int32_t *size,
+                       long long *acc, int32_t num_graphs, int *err, hipStream_t s);
+
+}  // namespace ccd

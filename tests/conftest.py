@@ -11,3 +11,14 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C ABI on the GPU)")
     config.addinivalue_line("markers", "slow: large CPU-only case")
+
+
+def _ensure_native():
+    """Build the in-tree libraries once if they are missing (CPU-only runs)."""
+    lib = os.path.join(ROOT, "paper_1507_05086_amd", "libcc.so")
+    if not os.path.exists(lib):
+        from paper_1507_05086_amd import build as ccbuild
+        ccbuild.build()
+
+
+_ensure_native()
