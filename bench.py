@@ -36,9 +36,11 @@ def make_graph(name):
 def algorithmic_bytes(st, n):
     """Bytes the method itself must move in one call (see the design notes):
     8 B per adjacency item scanned (4 B column + 4 B neighbour word) in the
-    election, claim and peel passes, 8 B per atomic read-modify-write, and
-    32 B per vertex (offsets, order, rank, initial state, final label)."""
-    return 8 * (st.scanned_elect + st.scanned_claim + st.scanned_peel) + 8 * st.atomics + 32 * n
+    election, claim, degree-refresh and peel passes, 8 B per atomic
+    read-modify-write, and 32 B per vertex (offsets, order, rank, initial
+    state, final label)."""
+    scanned = st.scanned_elect + st.scanned_claim + st.scanned_delta + st.scanned_peel
+    return 8 * scanned + 8 * st.atomics + 32 * n
 
 
 def cpu_baseline(sample):
@@ -124,7 +126,8 @@ def main():
         return {"loop_ms": round(loop, 3), "rounds": runs[-1].rounds, "edges_per_s": m / (loop / 1e3),
                 "alg_bytes": nbytes, "achieved_gbs": nbytes / (loop / 1e3) / 1e9,
                 "atomics": runs[-1].atomics,
-                "scanned": runs[-1].scanned_elect + runs[-1].scanned_claim + runs[-1].scanned_peel}
+                "scanned": {"elect": runs[-1].scanned_elect, "claim": runs[-1].scanned_claim,
+                            "delta": runs[-1].scanned_delta, "peel": runs[-1].scanned_peel}}
 
     s4, sw = summary(c4), summary(cw)
     dom = s4 if s4["loop_ms"] >= sw["loop_ms"] else sw

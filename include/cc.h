@@ -89,6 +89,7 @@ typedef struct cc_run_stats {
   int64_t scanned_elect; /* out: adjacency entries (+1 per isolated row) read by the C4 election */
   int64_t scanned_claim; /* out: adjacency entries (+1 per isolated row) read by claims */
   int64_t scanned_peel;  /* out: adjacency entries (+1 per isolated row) read by peeling */
+  int64_t scanned_delta; /* out: adjacency entries read to refresh remaining degrees (Delta) */
   int64_t blocked;       /* out: sum of conflicts over rounds */
   int64_t atomics;       /* out: atomic read-modify-writes (claims and degree decrements) */
   double loop_ms;        /* out: device time of the round loop (HIP events on `stream`) */

@@ -64,6 +64,7 @@ class _RoundRecord(ctypes.Structure):
 class _RunStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("scanned_elect", ctypes.c_int64),
                 ("scanned_claim", ctypes.c_int64), ("scanned_peel", ctypes.c_int64),
+                ("scanned_delta", ctypes.c_int64),
                 ("blocked", ctypes.c_int64), ("atomics", ctypes.c_int64),
                 ("loop_ms", ctypes.c_double), ("policy_fallback", ctypes.c_int32),
                 ("truncated", ctypes.c_int32), ("trace", ctypes.POINTER(_RoundRecord)),
@@ -187,6 +188,7 @@ class RunStats:
     scanned_elect: int = 0
     scanned_claim: int = 0
     scanned_peel: int = 0
+    scanned_delta: int = 0
     blocked: int = 0
     atomics: int = 0
     loop_ms: float = 0.0
@@ -213,7 +215,8 @@ def _run(fn, graph: Graph, order, eps, labels=None, trace_capacity=1 << 14, stre
         st.trace_capacity = trace_capacity
     _check(fn(graph.handle, po, float(eps), pl, ctypes.byref(st), flags, _stream(stream, order, labels)))
     out = RunStats(rounds=st.rounds, scanned_elect=st.scanned_elect, scanned_claim=st.scanned_claim,
-                   scanned_peel=st.scanned_peel, blocked=st.blocked, atomics=st.atomics,
+                   scanned_peel=st.scanned_peel, scanned_delta=st.scanned_delta, blocked=st.blocked,
+                   atomics=st.atomics,
                    loop_ms=st.loop_ms, policy_fallback=st.policy_fallback,
                    truncated=st.truncated)
     if rec is not None:

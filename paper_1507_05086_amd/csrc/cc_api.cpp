@@ -49,10 +49,18 @@ std::mutex g_policy_mu;
 // Device workspace of a run (allocated on the first run of a graph).
 struct Workspace {
   bool ready = false;
-  int32_t *rank = nullptr, *lab = nullptr, *resdeg = nullptr;
+  int32_t *rank = nullptr, *lab = nullptr, *ub = nullptr;
+  uint32_t *unc = nullptr;
   uint8_t *state = nullptr, *flag = nullptr;
   int32_t *alist = nullptr, *clist = nullptr, *nlist = nullptr, *blist = nullptr;
   int64_t *awork = nullptr, *cwork = nullptr, *nwork = nullptr;
+  int32_t *rlist = nullptr, *xlist = nullptr;
+  int64_t *rwork = nullptr, *xwork = nullptr;
+  unsigned long long *racc = nullptr;
+  int64_t rcap = 0;
+  int32_t *lvl = nullptr;
+  int *hist = nullptr;
+  int64_t hist_len = 0;
   int2 *cedge = nullptr;
   int64_t cedge_cap = 0;
   unsigned long long *tstat = nullptr;
@@ -81,6 +89,12 @@ struct cc_graph {
   int64_t *vtx_ptr = nullptr;  // device, batches only
   int32_t *gid = nullptr;      // device, batches only
   int64_t *wall = nullptr;     // device [n+1]
+  int64_t max_deg = 0;
+  int64_t n_hi = 0;            // vertices with degree >= DSW
+  int32_t *lvl_init = nullptr; // device: initial bound buckets
+  int64_t *lvl_off = nullptr;  // device [NLVL+1]
+  unsigned *lvl_cnt0 = nullptr;  // device [NLVL]: initial entries per level
+  int64_t lvl_total = 0;
   std::vector<int64_t> h_vtx_ptr;
   std::vector<int64_t> m_per_graph;
   Workspace ws;
@@ -89,9 +103,10 @@ struct cc_graph {
 namespace {
 
 void free_ws(Workspace &w) {
-  void *ptrs[] = {w.rank, w.lab, w.resdeg, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
-                  w.awork, w.cwork, w.nwork, w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf,
-                  w.label_buf, w.sched, w.mlp, w.cost_size, w.cost_acc, w.dev_err};
+  void *ptrs[] = {w.rank, w.lab, w.ub, w.unc, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
+                  w.awork, w.cwork, w.nwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist,
+                  w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf, w.label_buf, w.sched, w.mlp,
+                  w.cost_size, w.cost_acc, w.dev_err};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (w.host_flags) (void)hipHostFree(w.host_flags);
@@ -108,6 +123,9 @@ void free_graph(cc_graph *g) {
   if (g->vtx_ptr) (void)hipFree(g->vtx_ptr);
   if (g->gid) (void)hipFree(g->gid);
   if (g->wall) (void)hipFree(g->wall);
+  if (g->lvl_init) (void)hipFree(g->lvl_init);
+  if (g->lvl_off) (void)hipFree(g->lvl_off);
+  if (g->lvl_cnt0) (void)hipFree(g->lvl_cnt0);
   delete g;
 }
 
@@ -117,7 +135,8 @@ int32_t ensure_ws(cc_graph *g) {
   const int64_t n = g->n > 0 ? g->n : 1;
   HIP_TRY(dalloc(&w.rank, n));
   HIP_TRY(dalloc(&w.lab, n));
-  HIP_TRY(dalloc(&w.resdeg, n));
+  HIP_TRY(dalloc(&w.ub, n));
+  HIP_TRY(dalloc(&w.unc, (size_t)(n + 31) / 32));
   HIP_TRY(dalloc(&w.state, n));
   HIP_TRY(dalloc(&w.flag, n));
   HIP_TRY(dalloc(&w.alist, n));
@@ -127,6 +146,15 @@ int32_t ensure_ws(cc_graph *g) {
   HIP_TRY(dalloc(&w.awork, n));
   HIP_TRY(dalloc(&w.cwork, n));
   HIP_TRY(dalloc(&w.nwork, n));
+  w.rcap = g->n_hi + 1;
+  HIP_TRY(dalloc(&w.rlist, (size_t)(DITER * w.rcap)));
+  HIP_TRY(dalloc(&w.rwork, (size_t)(DITER * w.rcap)));
+  HIP_TRY(dalloc(&w.racc, (size_t)(DITER * w.rcap)));
+  HIP_TRY(dalloc(&w.xlist, n));
+  HIP_TRY(dalloc(&w.xwork, n));
+  HIP_TRY(dalloc(&w.lvl, (size_t)(g->lvl_total > 0 ? g->lvl_total : 1)));
+  w.hist_len = g->max_deg + 2;
+  HIP_TRY(dalloc(&w.hist, (size_t)w.hist_len));
   w.cedge_cap = n > (1 << 20) ? n : (1 << 20);
   HIP_TRY(dalloc(&w.cedge, (size_t)w.cedge_cap));
   w.tstat_cap = n / TSEL + 4096 + 2;
@@ -205,9 +233,11 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.col = g->col;
   w.n = n;
   w.order = d_order;
+  w.max_deg = g->max_deg;
   w.rank = ws.rank;
   w.lab = ws.lab;
-  w.resdeg = ws.resdeg;
+  w.ub = ws.ub;
+  w.unc = ws.unc;
   w.state = ws.state;
   w.flag = ws.flag;
   w.alist = ws.alist;
@@ -217,6 +247,15 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.awork = ws.awork;
   w.cwork = ws.cwork;
   w.nwork = ws.nwork;
+  w.rlist = ws.rlist;
+  w.rwork = ws.rwork;
+  w.racc = ws.racc;
+  w.rcap = ws.rcap;
+  w.xlist = ws.xlist;
+  w.xwork = ws.xwork;
+  w.lvl = ws.lvl;
+  w.lvl_off = g->lvl_off;
+  w.hist = ws.hist;
   w.cedge = ws.cedge;
   w.cedge_cap = ws.cedge_cap;
   w.tstat = ws.tstat;
@@ -237,7 +276,10 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   // init: the permutation is checked before any kernel indexes with it
   HIP_TRY(hipMemsetAsync(ws.ctrl, 0, sizeof(Ctrl), s));
   HIP_TRY(hipMemsetAsync(ws.rank, 0xFF, sizeof(int32_t) * (size_t)n, s));
-  HIP_TRY(launch_init(w, s));
+  HIP_TRY(hipMemsetAsync(ws.hist, 0, sizeof(int) * (size_t)ws.hist_len, s));
+  if (g->lvl_total > 0)
+    HIP_TRY(hipMemcpyAsync(ws.lvl, g->lvl_init, sizeof(int32_t) * (size_t)g->lvl_total, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_init(w, g->lvl_cnt0, s));
   HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (ws.host_flags[1] == ERR_PERM)
@@ -288,6 +330,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     stats->scanned_elect = (int64_t)hc.sum_elect;
     stats->scanned_claim = (int64_t)hc.sum_claim;
     stats->scanned_peel = (int64_t)hc.sum_peel;
+    stats->scanned_delta = (int64_t)hc.sum_rescan;
     stats->blocked = (int64_t)hc.sum_blocked;
     stats->atomics = (int64_t)hc.sum_atomics;
     float ms = 0.f;
@@ -422,6 +465,45 @@ int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_
   (void)hipFree(blocksum);
   (void)hipFree(derr);
   G_TRY(e);
+  if (herr == none && n_total > 0) {
+    // bound buckets: capacity of level k = vertices of degree >= 2^k
+    unsigned *dcnt = nullptr;
+    int *dmax = nullptr;
+    G_TRY(dalloc(&dcnt, NLVL));
+    G_TRY(dalloc(&dmax, 1));
+    G_TRY(hipMemsetAsync(dcnt, 0, sizeof(unsigned) * NLVL, s));
+    G_TRY(hipMemsetAsync(dmax, 0, sizeof(int), s));
+    G_TRY(launch_level_count(g->off, n_total, dcnt, dmax, s));
+    unsigned hcnt[NLVL];
+    int hmax = 0;
+    G_TRY(hipMemcpyAsync(hcnt, dcnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+    G_TRY(hipMemcpyAsync(&hmax, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
+    G_TRY(hipStreamSynchronize(s));
+    g->max_deg = hmax;
+    int64_t hoff[NLVL + 1];
+    int64_t acc = 0, hi = 0;
+    for (int k = 0; k < NLVL; k++) {
+      int64_t cap = 0;
+      if (k >= LVL_MIN)
+        for (int j = k; j < NLVL; j++) cap += hcnt[j];
+      hoff[k] = acc;
+      acc += cap;
+      hi += hcnt[k];
+    }
+    hoff[NLVL] = acc;
+    g->lvl_total = acc;
+    g->n_hi = hi;
+    G_TRY(dalloc(&g->lvl_off, NLVL + 1));
+    G_TRY(dalloc(&g->lvl_cnt0, NLVL));
+    G_TRY(dalloc(&g->lvl_init, (size_t)(acc > 0 ? acc : 1)));
+    G_TRY(hipMemcpyAsync(g->lvl_off, hoff, sizeof(hoff), hipMemcpyHostToDevice, s));
+    G_TRY(hipMemcpyAsync(g->lvl_cnt0, hcnt, sizeof(hcnt), hipMemcpyHostToDevice, s));
+    G_TRY(hipMemsetAsync(dcnt, 0, sizeof(unsigned) * NLVL, s));
+    G_TRY(launch_level_fill(g->off, n_total, g->lvl_off, dcnt, g->lvl_init, s));
+    G_TRY(hipStreamSynchronize(s));
+    (void)hipFree(dcnt);
+    (void)hipFree(dmax);
+  }
   if (herr != none) {
     herr &= 0xFF;
     const char *what = herr == CC_ERR_OUT_OF_RANGE ? "a column index lies outside its graph"

@@ -3,13 +3,15 @@
 //
 // Memory layout of a run (all in HBM, sized for one graph of n vertices and
 // nnz stored adjacency entries):
-//   rank   int32[n]  position of each vertex in pi (rank = order^-1)
-//   lab    int32[n]  clusterID: rank of the vertex's center, INF while unclustered
-//   resdeg int32[n]  remaining positive degree (unclustered neighbours)
-//   state  uint8[n]  UNCL / ACTIVE / CENTER / NONCENTER / CLUST (67 MB at 2^26
-//                    vertices: small enough to stay in the 256 MB Infinity Cache)
-//   flag   uint8[n]  per-round scratch mark (blocked / waiting / conflict)
-//   three work lists (active set, centers, newly clustered), each a vertex
+//   rank   int32[n]   position of each vertex in pi (rank = order^-1)
+//   lab    int32[n]   clusterID: rank of the vertex's center, INF while unclustered
+//   ub     int32[n]   remaining-degree bound: an upper bound while Delta is
+//                     large, the exact remaining degree once the run switches
+//   unc    uint32[n/32] one bit per vertex, set while it is unclustered (8 MB at
+//                     2^26 vertices: gathers stay in L2 / the Infinity Cache)
+//   state  uint8[n]   ACTIVE / CENTER / NONCENTER marks of the current round
+//   flag   uint8[n]   per-round scratch mark (blocked / waiting / conflict)
+//   work lists: active set, centers, newly clustered, rescans; each a vertex
 //   array plus the exclusive prefix of the row weights max(deg, 1), so that
 //   adjacency passes can hand out equal numbers of entries to every workgroup.
 #pragma once
@@ -26,11 +28,19 @@ constexpr int SIPT = 16;            // pi positions per thread in the active-set
 constexpr int TSEL = BS * SIPT;     // pi positions per scan tile
 constexpr int32_t INF = 0x7fffffff;
 
-enum : uint8_t { UNCL = 0, ACTIVE = 1, CENTER = 2, NONCENTER = 3, CLUST = 4 };
+enum : uint8_t { UNCL = 0, ACTIVE = 1, CENTER = 2, NONCENTER = 3 };
+constexpr int DSW = 64;            // bounds below this never need a bucket entry
+constexpr int LVL_MIN = 6;         // log2(DSW): lowest bucket level of the bound buckets
+constexpr int NLVL = 32;           // bucket levels (level = floor(log2(ub)))
+constexpr int DITER = 3;           // band passes of the lazy Delta search per round
+constexpr int SWL = 128;           // a band floor below this switches to exact degrees
+constexpr int HLDS = 256;          // degree-histogram bins kept per workgroup in LDS
+// pass j rescans candidates with bound >= ceil(BAND_j * T_j)
+__host__ __device__ inline float band_factor(int pass) { return pass == 0 ? 0.7f : (pass == 1 ? 0.3f : 0.05f); }
 enum : int { ALGO_C4 = 0, ALGO_CW = 1 };
 enum : int { POL_FIXED = 0, POL_LEARNED = 1, POL_TRACE = 2 };
 enum : int { ERR_NONE = 0, ERR_PERM = 5, ERR_NO_PROGRESS = 8, ERR_OVERFLOW = 11, ERR_LABEL = 12 };
-enum : int { FIN_CLASSIFY = 0, FIN_PEEL = 1, FIN_DELTA = 2, FIN_COST = 3, FIN_N = 8 };
+enum : int { PHASE_LAZY = 0, PHASE_EXACT = 1 };
 
 // A list is packed in one 64-bit counter: (total weight << 31) | count, so a
 // single atomic reserves both a slot range and its weight range, and the
@@ -50,31 +60,36 @@ struct RoundRec {  // mirrors cc_round_record
 struct Ctrl {
   // carried across rounds
   long long n_rem;         // unclustered vertices
-  long long delta;         // max remaining degree (current round)
+  long long delta;         // Delta_i of the current round
   long long cursor;        // first pi position not yet passed
   long long b;             // active-set size of the current round
   long long round;         // rounds finished
   long long n_start;       // n_i of the current round
   long long r_last;        // rank of the last active vertex
   int done, error;
-  int has_round;           // the delta kernel closes a round (0 before round 0)
+  int has_round;           // a round has been run since the start
   int fallback;            // learned policy fell back to the fixed rule
+  int phase;               // PHASE_LAZY (upper bounds) or PHASE_EXACT (exact degrees)
+  int pad0;
   double eps_used;         // eps behind b
   float feat_conf, feat_claim, feat_eps;  // previous-round features for the learned policy
-  int pad0;
+  int pad1;
   long long t_start;       // wall clock at round start
   // per round
   unsigned long long a_pack, c_pack, n_pack;  // active / center / newly lists
   unsigned int tile_counter;
   int select_done;
   unsigned int n_blocked, n_cedges;
-  int delta_next;
-  int pad1;
   unsigned long long conflicts;
-  unsigned int fin[FIN_N];  // last-workgroup counters, one per kernel kind
+  // lazy Delta search: per band pass, the rescan list and the largest exact degree found
+  unsigned long long r_pack[DITER];
+  int d_max[DITER];
+  int pad2;
+  unsigned long long x_pack;  // rows recounted when switching to exact degrees
+  // bound buckets: entries per level (capacity fixed per graph)
+  unsigned int lvl_cnt[NLVL];
   // run totals
-  unsigned long long sum_elect, sum_claim, sum_peel, sum_blocked, sum_atomics;
-  long long trace_written;
+  unsigned long long sum_elect, sum_claim, sum_rescan, sum_peel, sum_blocked, sum_atomics;
 };
 
 struct Ws {
@@ -82,18 +97,26 @@ struct Ws {
   const int64_t *off;
   const int32_t *col;
   int64_t n;
+  int64_t max_deg;
   // run input
   const int32_t *order;
   // per-vertex arrays
-  int32_t *rank, *lab, *resdeg;
+  int32_t *rank, *lab, *ub;
+  uint32_t *unc;
   uint8_t *state, *flag;
   // lists
-  int32_t *alist, *clist, *nlist, *blist;
-  int64_t *awork, *cwork, *nwork;
+  int32_t *alist, *clist, *nlist, *blist, *rlist, *xlist;
+  int64_t *awork, *cwork, *nwork, *rwork, *xwork;
+  unsigned long long *racc;  // rescan accumulators (items covered << 32 | count), DITER * rcap
+  int64_t rcap;         // capacity of one pass's rescan list
   int2 *cedge;
   int64_t cedge_cap;
   unsigned long long *tstat;
   int64_t tstat_cap;
+  // bound buckets
+  int32_t *lvl;         // entries of all levels
+  const int64_t *lvl_off;  // [NLVL+1] start of each level in lvl (device)
+  int *hist;            // exact phase: vertices per remaining degree, [max_deg + 1]
   Ctrl *ctrl;
   RoundRec *trace;
   int64_t trace_cap;
@@ -107,6 +130,15 @@ struct Ws {
   const float *mlp;     // LEARNED: 6-64-1 weights (device)
   float eps_min, eps_max;
 };
+
+__host__ __device__ inline int level_of(int64_t x) {  // floor(log2(x)), x >= 1
+  int l = 0;
+  while ((x >> 1) > 0) {
+    x >>= 1;
+    l++;
+  }
+  return l;
+}
 
 // ------------------------------------------------------------- atomics ----
 
@@ -215,19 +247,6 @@ __device__ inline int64_t wave_find_entry(const int64_t *work, int64_t cnt, int6
   return lo;
 }
 
-// Last-workgroup detection: returns true in exactly one workgroup (the last
-// to arrive), after all others have made their writes visible.
-__device__ inline bool last_block(unsigned int *counter) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
+__device__ inline bool unc_bit(const uint32_t *unc, int32_t v) { return (unc[v >> 5] >> (v & 31)) & 1u; }
 
 }  // namespace ccd

@@ -153,6 +153,71 @@ hipError_t launch_graph_setup(const int64_t *off, const int32_t *col, int64_t n,
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ bound buckets ----
+
+__global__ void __launch_bounds__(BS) k_level_count(const int64_t *off, int64_t n, unsigned *count, int *max_deg) {
+  __shared__ unsigned s_cnt[NLVL];
+  __shared__ int s_max;
+  if (threadIdx.x < NLVL) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  int mx = 0;
+  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
+    const int64_t d = off[v + 1] - off[v];
+    if (d > mx) mx = (int)d;
+    if (d >= DSW) atomicAdd(&s_cnt[level_of(d)], 1u);
+  }
+  mx = wave_max(mx);
+  if (lane_id() == 0) atomicMax(&s_max, mx);
+  __syncthreads();
+  if (threadIdx.x < NLVL && s_cnt[threadIdx.x]) atomicAdd(&count[threadIdx.x], s_cnt[threadIdx.x]);
+  if (threadIdx.x == 0 && s_max) atomicMax(max_deg, s_max);
+}
+
+// Each workgroup takes a contiguous chunk: counts per level in LDS, reserves
+// its ranges with one atomic per level, then writes.
+__global__ void __launch_bounds__(BS) k_level_fill(const int64_t *off, int64_t n, const int64_t *lvl_off,
+                                                   unsigned *cursor, int32_t *lvl) {
+  __shared__ unsigned s_cnt[NLVL], s_base[NLVL];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t v0 = (int64_t)blockIdx.x * per, v1 = v0 + per < n ? v0 + per : n;
+  if (threadIdx.x < NLVL) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += BS) {
+    const int64_t d = off[v + 1] - off[v];
+    if (d >= DSW) atomicAdd(&s_cnt[level_of(d)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < NLVL) {
+    s_base[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], s_cnt[threadIdx.x]) : 0u;
+    s_cnt[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += BS) {
+    const int64_t d = off[v + 1] - off[v];
+    if (d >= DSW) {
+      const int k = level_of(d);
+      const unsigned p = s_base[k] + atomicAdd(&s_cnt[k], 1u);
+      lvl[lvl_off[k] + p] = (int32_t)v;
+    }
+  }
+}
+
+hipError_t launch_level_count(const int64_t *off, int64_t n, unsigned *count, int *max_deg, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t g = (n + BS - 1) / BS < 2048 ? (n + BS - 1) / BS : 2048;
+  hipLaunchKernelGGL(k_level_count, dim3((unsigned)g), dim3(BS), 0, s, off, n, count, max_deg);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_fill(const int64_t *off, int64_t n, const int64_t *lvl_off, unsigned *cursor,
+                             int32_t *lvl, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t g = (n + BS - 1) / BS < 4096 ? (n + BS - 1) / BS : 4096;
+  hipLaunchKernelGGL(k_level_fill, dim3((unsigned)g), dim3(BS), 0, s, off, n, lvl_off, cursor, lvl);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ cost --
 
 struct CostArgs {

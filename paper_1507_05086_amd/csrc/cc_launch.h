@@ -13,7 +13,7 @@ struct LaunchShape {
   unsigned scan_grid;    // cap on workgroups of the full-vertex delta scan
 };
 
-hipError_t launch_init(const Ws &w, hipStream_t s);
+hipError_t launch_init(const Ws &w, const unsigned *lvl_init_cnt, hipStream_t s);
 hipError_t launch_round(const Ws &w, hipStream_t s, const LaunchShape &ls);
 hipError_t launch_finalize(const Ws &w, int32_t *labels, hipStream_t s);
 
@@ -24,6 +24,13 @@ hipError_t launch_finalize(const Ws &w, int32_t *labels, hipStream_t s);
 hipError_t launch_graph_setup(const int64_t *off, const int32_t *col, int64_t n, const int64_t *vtx_ptr,
                               int32_t num_graphs, int32_t *gid, int64_t *wall, int64_t *blocksum,
                               int validate, int *err, hipStream_t s);
+
+// Bucket levels of the degree bounds: count[k] = vertices with
+// floor(log2(deg)) == k (k >= LVL_MIN), and the maximum degree.
+hipError_t launch_level_count(const int64_t *off, int64_t n, unsigned *count, int *max_deg, hipStream_t s);
+// Places every vertex with deg >= DSW at lvl[lvl_off[k] + i], k = its level.
+hipError_t launch_level_fill(const int64_t *off, int64_t n, const int64_t *lvl_off, unsigned *cursor,
+                             int32_t *lvl, hipStream_t s);
 
 // Disagreement cost per graph: acc[2g] = pairs inside clusters, acc[2g+1] =
 // same-label adjacency entries (2 m_in); size is scratch [n].

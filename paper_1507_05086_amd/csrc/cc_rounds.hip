@@ -1,27 +1,48 @@
 // cc_rounds.hip -- the bulk-synchronous round loop of C4 and ClusterWild!
-// (arXiv 1507.05086, Algorithm 2) as a sequence of gfx950 kernels per round:
+// (arXiv 1507.05086, Algorithm 2) as a fixed sequence of gfx950 kernels per
+// round.  Kernel boundaries are the round's barriers (cheaper on this GPU than
+// a software grid barrier); every kernel returns at once when its part of the
+// round has nothing to do, so the host can queue rounds in groups and look at
+// the done flag once per group.
 //
 //   select    next B_i unclustered vertices of pi (lazy deletion: a cursor
 //             walks pi once); one pass with decoupled look-back
-//   elect     C4 only: does an active vertex have an earlier-ranked active
+//   elect     C4: does an active vertex have an earlier-ranked active
 //             neighbour?  (concurrency rule 1; edge-balanced)
-//   classify  C4 only: roots become centers; the last workgroup resolves the
-//             blocked ones as a fixed point over the conflict edges (the
-//             greedy MIS of G[A] in pi order, wait-free)
-//   claim     every center claims its eligible neighbours with atomicMin on
+//   classify  C4: roots become centers, the others are blocked
+//   resolve   C4: one workgroup settles the blocked vertices as a fixed point
+//             over the conflict edges (the greedy MIS of G[A] in pi order)
+//   claim     every center claims its unclustered neighbours with atomicMin on
 //             the center rank (concurrency rule 2, createCluster)
-//   peel      clustered vertices leave; their unclustered neighbours lose one
-//             remaining degree each (lazy deletion: the CSR is never changed)
-//   delta     max remaining degree Delta_{i+1}; the last workgroup closes the
-//             round (trace record) and sizes the next active set
+//   clear     the newly clustered leave the unclustered bitmap
+//   peel      exact phase only: neighbours of the newly clustered lose one
+//             remaining degree each (degree histogram kept per workgroup)
+//   dscan / rescan (x3)   lazy phase: the next Delta from stale upper bounds,
+//             rescanning only candidates in a band below the current Delta
+//   xlist / xcount        switch to exact degrees when the band gets low
+//   close     one workgroup: round record, Delta_{i+1}, B_{i+1}, counters
 //
-// Every kernel returns at once when the run is done, so the host can queue
-// rounds in groups and look at the done flag once per group.
+// The paper deletes lazily (clustered vertices are skipped, the graph is never
+// changed); here that extends to the remaining degrees: while Delta is large
+// they are upper bounds refreshed only where the maximum could be, and the
+// edge-by-edge peeling starts only when little of the graph is left.
 #include "cc_device.h"
 #include "cc_launch.h"
 #include "cc_walk.h"
 
 namespace ccd {
+
+// Per-row partial counts of rows split across tiles: one 64-bit atomic adds
+// (items covered << 32 | count); the contributor that completes the row
+// (covered == degree) owns the total.
+__device__ inline bool row_combine(unsigned long long *acc, int64_t slot, int cnt, int64_t covered, int32_t deg,
+                                   int *total) {
+  const unsigned long long add = ((unsigned long long)covered << 32) | (unsigned)cnt;
+  const unsigned long long tot = atomicAdd(&acc[slot], add) + add;
+  if ((int64_t)(tot >> 32) != (int64_t)deg) return false;
+  *total = (int)(tot & 0xFFFFFFFFu);
+  return true;
+}
 
 // ------------------------------------------------------------------ init --
 
@@ -38,20 +59,29 @@ __global__ void __launch_bounds__(BS) k_invert(Ws w) {
   }
 }
 
-__global__ void __launch_bounds__(BS) k_init(Ws w) {
+__global__ void __launch_bounds__(BS) k_init(Ws w, const unsigned *lvl_init_cnt) {
   const int64_t n = w.n;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
     w.lab[v] = INF;
     w.state[v] = UNCL;
     w.flag[v] = 0;
-    w.resdeg[v] = (int32_t)(w.off[v + 1] - w.off[v]);
+    w.ub[v] = (int32_t)(w.off[v + 1] - w.off[v]);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Ctrl *c = w.ctrl;
-    c->n_rem = n;
-    c->n_start = n;
-    c->done = (n == 0);
-    c->feat_eps = (float)w.eps;
+  const int64_t nw = (n + 31) / 32;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < nw; i += (int64_t)gridDim.x * BS) {
+    const int64_t rem = n - i * 32;
+    w.unc[i] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+  }
+  Ctrl *c = w.ctrl;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < NLVL) c->lvl_cnt[threadIdx.x] = lvl_init_cnt[threadIdx.x];
+    if (threadIdx.x == 0) {
+      c->n_rem = n;
+      c->n_start = n;
+      c->done = (n == 0);
+      c->phase = PHASE_LAZY;
+      c->feat_eps = (float)w.eps;
+    }
   }
 }
 
@@ -114,6 +144,251 @@ __device__ void next_batch(const Ws &w, long long n_rem, long long delta, long l
   *eps_out = eps_used;
 }
 
+// ------------------------------------------------- lazy Delta search -----
+// Pass j rescans every candidate whose bound is >= L_j = ceil(f_j * T_j)
+// (T_0 = Delta_i; f = 0.7, 0.3, 0.05).  Every other vertex has a bound below
+// L_j, so if the largest exact degree found is >= L_j it is Delta_{i+1};
+// otherwise T_{j+1} = L_j - 1.  When a band floor would fall below SWL, or all
+// passes fail, the run switches to exact remaining degrees.
+
+struct DSearch {
+  int pending;      // 1 while the search still needs the next pass
+  int switching;    // 1 when the run moves to exact degrees
+  long long delta;  // resolved Delta (when neither pending nor switching)
+  long long T, L;   // bounds of the pending pass
+};
+
+__device__ inline long long band_floor(int pass, long long T) {
+  return (long long)ceilf(band_factor(pass) * (float)T);
+}
+
+// State of the search after `done` passes (every thread computes the same).
+__device__ inline DSearch dsearch(const Ctrl *c, int done) {
+  DSearch s{0, 0, -1, 0, 0};
+  if (c->phase != PHASE_LAZY) return s;
+  long long T = c->delta;
+  for (int j = 0; j < done; j++) {
+    const long long L = band_floor(j, T);
+    if (L < SWL) {  // pass j never ran: the search switched before it
+      s.switching = 1;
+      return s;
+    }
+    const long long M = c->d_max[j];
+    if (M >= L) {
+      s.delta = M;
+      return s;
+    }
+    T = L - 1;
+  }
+  if (done >= DITER || band_floor(done, T) < SWL) {
+    s.switching = 1;
+    return s;
+  }
+  s.pending = 1;
+  s.T = T;
+  s.L = band_floor(done, T);
+  return s;
+}
+
+// Candidates of pass IT: live entries with bound >= L, found in the levels
+// level(L) .. top (a bound can be stale above the current Delta).
+template <int IT>
+__global__ void __launch_bounds__(BS) k_dscan(Ws w) {
+  Ctrl *c = w.ctrl;
+  if (c->done) return;
+  const DSearch s = dsearch(c, IT);
+  if (!s.pending) return;
+  const int kL = level_of(s.L < DSW ? DSW : s.L), kT = NLVL - 1;
+  int64_t base[NLVL + 1];
+  int64_t tot = 0;
+  for (int k = kL; k <= kT; k++) {
+    base[k] = tot;
+    const int64_t cap = w.lvl_off[k + 1] - w.lvl_off[k];
+    const int64_t cnt = c->lvl_cnt[k];
+    tot += cnt < cap ? cnt : cap;
+  }
+  base[kT + 1] = tot;
+  int32_t *rl = w.rlist + IT * w.rcap;
+  int64_t *rw = w.rwork + IT * w.rcap;
+  unsigned long long *ra = w.racc + IT * w.rcap;
+  for (int64_t i0 = (int64_t)blockIdx.x * BS; i0 < tot; i0 += (int64_t)gridDim.x * BS) {
+    const int64_t i = i0 + threadIdx.x;
+    int32_t v = 0;
+    bool take = false;
+    if (i < tot) {
+      int k = kL;
+      while (k < kT && i >= base[k + 1]) k++;
+      v = w.lvl[w.lvl_off[k] + (i - base[k])];
+      const int32_t x = w.ub[v];
+      take = x >= s.L && level_of(x) == k && unc_bit(w.unc, v);  // live entry, inside the band
+    }
+    const unsigned long long m = __ballot(take);
+    if (m) {
+      const int64_t d = take ? (w.off[v + 1] - w.off[v]) : 0;
+      const int64_t winc = wave_incl_scan(d);
+      const int64_t wtot = __shfl(winc, 63, 64);
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long b0 = 0;
+      if (lane_id() == leader) b0 = atomicAdd(&c->r_pack[IT], pk(wtot, __popcll(m)));
+      b0 = __shfl(b0, leader, 64);
+      if (take) {
+        const int64_t slot = pk_cnt(b0) + __popcll(m & lanemask_lt());
+        if (slot < w.rcap) {
+          rl[slot] = v;
+          rw[slot] = pk_work(b0) + winc - d;
+          ra[slot] = 0;
+        } else {
+          set_error(c, ERR_OVERFLOW);
+        }
+      }
+    }
+  }
+}
+
+// Exact remaining degrees of the pass's candidates; the new bounds move
+// entries down the levels; the pass maximum goes to d_max.
+template <int IT>
+__global__ void __launch_bounds__(BS) k_rescan(Ws w) {
+  Ctrl *c = w.ctrl;
+  if (c->done) return;
+  const DSearch s = dsearch(c, IT);
+  if (!s.pending) return;
+  __shared__ int lcnt[TW];
+  __shared__ int s_max, s_nmv;
+  __shared__ int s_mvn[NLVL], s_mvbase[NLVL];
+  __shared__ int32_t s_mv[TW];
+  __shared__ int8_t s_mvk[TW];
+  for (int i = threadIdx.x; i < TW; i += BS) lcnt[i] = 0;
+  if (threadIdx.x < NLVL) s_mvn[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    s_max = 0;
+    s_nmv = 0;
+  }
+  __syncthreads();
+  const unsigned long long rp = c->r_pack[IT];
+  const int64_t cnt = pk_cnt(rp) < w.rcap ? pk_cnt(rp) : w.rcap;
+  unsigned long long *ra = w.racc + IT * w.rcap;
+  auto finalize = [&](int32_t v, int r) {
+    const int32_t old = w.ub[v];
+    w.ub[v] = r;
+    atomicMax(&s_max, r);
+    const int kn = r >= DSW ? level_of(r) : -1;
+    if (kn >= 0 && kn != level_of(old)) {
+      const int p = atomicAdd(&s_nmv, 1);
+      s_mv[p] = v;
+      s_mvk[p] = (int8_t)kn;
+      atomicAdd(&s_mvn[kn], 1);
+    }
+  };
+  lb_walk(
+      w.rlist + IT * w.rcap, w.rwork + IT * w.rcap, cnt, pk_work(rp), w.off, w.col, nullptr,
+      [&](Items &it) {
+#pragma unroll
+        for (int k = 0; k < IPT; k++)
+          if ((it.edge >> k & 1) && unc_bit(w.unc, it.u[k])) atomicAdd(&lcnt[it.ent[k]], 1);
+      },
+      [&](int j, int64_t slot, int32_t v, int32_t deg, int64_t covered) {
+        const int cj = lcnt[j];
+        lcnt[j] = 0;
+        int total = cj;
+        if (covered == deg || row_combine(ra, slot, cj, covered, deg, &total)) finalize(v, total);
+      },
+      [&]() {
+        // this tile's level moves: one reservation per level, then the writes
+        __syncthreads();
+        if (threadIdx.x < NLVL && s_mvn[threadIdx.x]) {
+          const int k = threadIdx.x;
+          s_mvbase[k] = (int)atomicAdd(&c->lvl_cnt[k], (unsigned)s_mvn[k]);
+        }
+        __syncthreads();
+        const int nmv = s_nmv;
+        for (int p = threadIdx.x; p < nmv; p += BS) {
+          const int k = s_mvk[p];
+          int q = 0;  // rank among this tile's earlier moves to the same level
+          for (int x = 0; x < p; x++) q += (s_mvk[x] == k);
+          const int64_t pos = (int64_t)s_mvbase[k] + q;
+          if (pos < w.lvl_off[k + 1] - w.lvl_off[k]) w.lvl[w.lvl_off[k] + pos] = s_mv[p];
+          else set_error(c, ERR_OVERFLOW);
+        }
+        __syncthreads();
+        if (threadIdx.x < NLVL) s_mvn[threadIdx.x] = 0;
+        if (threadIdx.x == 0) s_nmv = 0;
+      });
+  __syncthreads();
+  if (threadIdx.x == 0 && s_max > 0) atomicMax(&c->d_max[IT], s_max);
+}
+
+// Switch to exact degrees: list the unclustered rows (their accumulators
+// live in the active-list weights, free at this point of the round) ...
+__global__ void __launch_bounds__(BS) k_xlist(Ws w) {
+  Ctrl *c = w.ctrl;
+  if (c->done) return;
+  const DSearch s = dsearch(c, DITER);
+  if (!s.switching) return;
+  unsigned long long *xacc = (unsigned long long *)w.awork;
+  const int64_t n = w.n;
+  for (int64_t v0 = (int64_t)blockIdx.x * BS; v0 < n; v0 += (int64_t)gridDim.x * BS) {
+    const int64_t v = v0 + threadIdx.x;
+    bool take = false;
+    int64_t d = 0;
+    if (v < n && unc_bit(w.unc, (int32_t)v)) {
+      d = w.off[v + 1] - w.off[v];
+      take = d > 0;
+    }
+    const unsigned long long m = __ballot(take);
+    if (m) {
+      const int64_t winc = wave_incl_scan(d * take);
+      const int64_t wtot = __shfl(winc, 63, 64);
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long b0 = 0;
+      if (lane_id() == leader) b0 = atomicAdd(&c->x_pack, pk(wtot, __popcll(m)));
+      b0 = __shfl(b0, leader, 64);
+      if (take) {
+        const int64_t slot = pk_cnt(b0) + __popcll(m & lanemask_lt());
+        w.xlist[slot] = (int32_t)v;
+        w.xwork[slot] = pk_work(b0) + winc - d;
+        xacc[slot] = 0;
+      }
+    }
+  }
+}
+
+// ... and count their unclustered neighbours into ub and the histogram.
+__global__ void __launch_bounds__(BS) k_xcount(Ws w) {
+  Ctrl *c = w.ctrl;
+  if (c->done) return;
+  const DSearch s = dsearch(c, DITER);
+  if (!s.switching) return;
+  __shared__ int lcnt[TW];
+  __shared__ int s_hist[HLDS];
+  for (int i = threadIdx.x; i < TW; i += BS) lcnt[i] = 0;
+  for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
+  __syncthreads();
+  unsigned long long *xacc = (unsigned long long *)w.awork;
+  const unsigned long long xp = c->x_pack;
+  auto finalize = [&](int32_t v, int r) {
+    w.ub[v] = r;
+    if (r > 0 && r < HLDS) atomicAdd(&s_hist[r], 1);
+    else if (r >= HLDS) atomicAdd(&w.hist[r], 1);
+  };
+  lb_walk(
+      w.xlist, w.xwork, pk_cnt(xp), pk_work(xp), w.off, w.col, nullptr,
+      [&](Items &it) {
+#pragma unroll
+        for (int k = 0; k < IPT; k++)
+          if ((it.edge >> k & 1) && unc_bit(w.unc, it.u[k])) atomicAdd(&lcnt[it.ent[k]], 1);
+      },
+      [&](int j, int64_t slot, int32_t v, int32_t deg, int64_t covered) {
+        const int cj = lcnt[j];
+        lcnt[j] = 0;
+        int total = cj;
+        if (covered == deg || row_combine(xacc, slot, cj, covered, deg, &total)) finalize(v, total);
+      });
+  __syncthreads();
+  for (int i = threadIdx.x; i < HLDS; i += BS)
+    if (s_hist[i]) atomicAdd(&w.hist[i], s_hist[i]);
+}
+
 // ------------------------------------------------------------- select -----
 // Tile status word: bits 63..62 = 1 (aggregate) or 2 (inclusive prefix),
 // bits 61..0 = value.  Tiles are handed out in order by an atomic counter, so
@@ -148,8 +423,15 @@ __global__ void __launch_bounds__(BS) k_select(Ws w) {
   __shared__ int s_stop;
   __shared__ long long s_excl;
   __shared__ int64_t sh[WAVES + 1];
+  __shared__ unsigned long long s_base;
   const long long B = c->b, cur0 = c->cursor;
   const int64_t n = w.n;
+  // Workgroups this round can use: B_i unclustered are spread over the
+  // positions ahead with density n_i / (n - cursor); extra groups would only
+  // grab tiles past the end of the active set.
+  const long long ahead = n - cur0, n_i = c->n_rem > 0 ? c->n_rem : 1;
+  const long long need_pos = (long long)((double)B * (double)ahead / (double)n_i) + TSEL;
+  if ((long long)blockIdx.x > need_pos / TSEL) return;
   for (;;) {
     if (threadIdx.x == 0) {
       s_stop = ld_acq(&c->select_done);
@@ -173,7 +455,7 @@ __global__ void __launch_bounds__(BS) k_select(Ws w) {
 #pragma unroll
     for (int k = 0; k < SIPT; k++) {
       const int64_t p = base + k;
-      if (p < n && w.state[vv[k]] == UNCL) un |= 1u << k;
+      if (p < n && unc_bit(w.unc, vv[k])) un |= 1u << k;
     }
     int64_t agg;
     const int64_t mine = wg_excl_scan(__popc(un), &agg, sh);
@@ -213,7 +495,6 @@ __global__ void __launch_bounds__(BS) k_select(Ws w) {
     int64_t wtot, ctot;
     const int64_t wpre = wg_excl_scan(wsum, &wtot, sh);
     const int64_t cpre = wg_excl_scan(cnt, &ctot, sh);
-    __shared__ unsigned long long s_base;
     if (threadIdx.x == 0 && ctot > 0) s_base = atomicAdd(&c->a_pack, pk(wtot, ctot));
     __syncthreads();
     if (ctot > 0) {
@@ -245,10 +526,11 @@ __global__ void __launch_bounds__(BS) k_elect(Ws w) {
   lb_walk(w.alist, w.awork, pk_cnt(ap), pk_work(ap), w.off, w.col, w.rank, [&](Items &it) {
     uint8_t su[IPT];
 #pragma unroll
-    for (int k = 0; k < IPT; k++) su[k] = (it.edge >> k & 1) ? w.state[it.u[k]] : (uint8_t)CLUST;
+    for (int k = 0; k < IPT; k++) su[k] = (it.edge >> k & 1) ? w.state[it.u[k]] : (uint8_t)UNCL;
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
       bool conf = false;
+      // an ACTIVE mark is always this round's: C4 settles every active vertex
       if (su[k] == ACTIVE) conf = w.rank[it.u[k]] < it.val[k];  // earlier-ranked active neighbour
       if (conf) w.flag[it.v[k]] = 1;
       const unsigned long long m = __ballot(conf);
@@ -266,11 +548,7 @@ __global__ void __launch_bounds__(BS) k_elect(Ws w) {
   });
 }
 
-// Roots (no earlier active neighbour) are centers at once; the last
-// workgroup then settles the blocked vertices: a blocked vertex is a
-// non-center as soon as an earlier active neighbour is a center, and a center
-// once all of them are non-centers.  Each sweep settles at least the
-// lowest-ranked undecided vertex, so it ends.
+// Roots (no earlier active neighbour) are centers at once; the rest wait.
 __global__ void __launch_bounds__(BS) k_classify(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
@@ -298,15 +576,23 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
       if (blocked) w.blist[base + __popcll(m & lanemask_lt())] = a;
     }
   }
-  if (!last_block(&c->fin[FIN_CLASSIFY])) return;
-  // ---- resolve (one workgroup) ----
-  const int64_t nb = ld_acq(&c->n_blocked);
-  const int64_t ne_all = ld_acq(&c->n_cedges);
+}
+
+// One workgroup: a blocked vertex is a non-center as soon as an earlier
+// active neighbour is a center, and a center once all of them are
+// non-centers.  Each sweep settles at least the lowest-ranked undecided
+// vertex, so it ends.
+__global__ void __launch_bounds__(BS) k_resolve(Ws w) {
+  Ctrl *c = w.ctrl;
+  if (c->done) return;
+  const int64_t nb = c->n_blocked;
+  if (nb == 0) return;
+  const int64_t ne_all = c->n_cedges;
   __shared__ int s_any;
   if (ne_all <= w.cedge_cap) {
     // conflict edges (a, u): u is an earlier-ranked active neighbour of a
     const int64_t ne = ne_all;
-    for (int64_t iter = 0; iter <= nb && nb > 0; iter++) {
+    for (int64_t iter = 0; iter <= nb; iter++) {
       for (int64_t i = threadIdx.x; i < ne; i += BS) {
         const int2 e = w.cedge[i];
         if (w.state[e.x] == ACTIVE && w.state[e.y] == CENTER) w.state[e.x] = NONCENTER;
@@ -345,7 +631,7 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
   } else {
     // too many conflict edges to list: rescan the rows of the blocked vertices
     // (every earlier-ranked unclustered neighbour of an active vertex is active)
-    for (int64_t iter = 0; iter <= nb && nb > 0; iter++) {
+    for (int64_t iter = 0; iter <= nb; iter++) {
       if (threadIdx.x == 0) s_any = 0;
       __syncthreads();
       for (int64_t i0 = 0; i0 < nb; i0 += BS) {
@@ -359,12 +645,11 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
             bool center_before = false, undecided_before = false;
             for (int64_t e = w.off[a]; e < w.off[a + 1] && !center_before; e++) {
               const int32_t u = w.col[e];
+              if (!unc_bit(w.unc, u)) continue;
               const uint8_t su = w.state[u];
-              if (su == CENTER || su == ACTIVE) {
-                if (w.rank[u] < ra) {
-                  if (su == CENTER) center_before = true;
-                  else undecided_before = true;
-                }
+              if ((su == CENTER || su == ACTIVE) && w.rank[u] < ra) {
+                if (su == CENTER) center_before = true;
+                else undecided_before = true;
               }
             }
             if (center_before) w.state[a] = NONCENTER;
@@ -383,7 +668,6 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
     }
   }
   for (int64_t i = threadIdx.x; i < nb; i += BS) w.flag[w.blist[i]] = 0;
-  if (threadIdx.x == 0) c->fin[FIN_CLASSIFY] = 0;
 }
 
 // -------------------------------------------------------------- claim -----
@@ -405,15 +689,18 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
       const bool vt = it.vert >> k & 1;
       wave_append(vt, it.v[k], it.deg[k] > 0 ? it.deg[k] : 1, &c->n_pack, w.nlist, w.nwork);
     }
-    uint8_t su[IPT];
+    bool un[IPT];
 #pragma unroll
-    for (int k = 0; k < IPT; k++) su[k] = (it.edge >> k & 1) ? w.state[it.u[k]] : (uint8_t)CLUST;
-    int32_t cur[IPT];
+    for (int k = 0; k < IPT; k++) un[k] = (it.edge >> k & 1) && unc_bit(w.unc, it.u[k]);
     bool elig[IPT];
+    int32_t cur[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
-      elig[k] = c4 ? (su[k] == UNCL || su[k] == NONCENTER) : (su[k] == UNCL);
-      if (!c4 && su[k] == ACTIVE && w.rank[it.u[k]] < it.val[k]) w.flag[it.v[k]] = 1;  // rule 1 broken
+      elig[k] = un[k];
+      if (!c4 && un[k] && w.state[it.u[k]] == ACTIVE) {  // ClusterWild! claims Gamma(c) \ A
+        elig[k] = false;
+        if (w.rank[it.u[k]] < it.val[k]) w.flag[it.v[k]] = 1;  // rule 1 broken
+      }
       cur[k] = elig[k] ? w.lab[it.u[k]] : 0;  // stale reads are safe: labels only decrease
     }
 #pragma unroll
@@ -433,79 +720,89 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   if (threadIdx.x == 0 && s_atom) atomicAdd(&c->sum_atomics, (unsigned long long)s_atom);
 }
 
+// The newly clustered leave the unclustered bitmap; ClusterWild! conflict
+// marks are counted; the scan tiles of this round are forgotten.
+__global__ void __launch_bounds__(BS) k_clear(Ws w) {
+  Ctrl *c = w.ctrl;
+  if (c->done) return;
+  const int64_t nn = pk_cnt(c->n_pack);
+  const bool cw = w.algo == ALGO_CW;
+  unsigned conf = 0;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < nn; i += (int64_t)gridDim.x * BS) {
+    const int32_t u = w.nlist[i];
+    atomicAnd(&w.unc[u >> 5], ~(1u << (u & 31)));
+    if (cw && w.flag[u]) {
+      w.flag[u] = 0;
+      conf++;
+    }
+  }
+  const int64_t tiles = (int64_t)c->tile_counter + 1;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < tiles && t < w.tstat_cap;
+       t += (int64_t)gridDim.x * BS)
+    w.tstat[t] = 0;
+  if (cw) {
+    const int64_t s = wave_sum((int64_t)conf);
+    if (lane_id() == 0 && s) atomicAdd(&c->conflicts, (unsigned long long)s);
+  }
+}
+
 // --------------------------------------------------------------- peel -----
+// Exact phase: every unclustered neighbour of a newly clustered vertex loses
+// one remaining degree; the degree histogram follows (low bins per workgroup).
+__device__ inline void hist_add(int *s_hist, int *g_hist, int d, int x) {
+  if (d <= 0) return;
+  if (d < HLDS) atomicAdd(&s_hist[d], x);
+  else atomicAdd(&g_hist[d], x);
+}
 
 __global__ void __launch_bounds__(BS) k_peel(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
-  const unsigned long long np = c->n_pack;
-  const bool cw = w.algo == ALGO_CW;
-  __shared__ unsigned s_conf, s_atom;
-  if (threadIdx.x == 0) s_conf = s_atom = 0;
+  if (c->done || c->phase != PHASE_EXACT) return;
+  __shared__ int s_hist[HLDS];
+  __shared__ unsigned s_atom;
+  for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
+  if (threadIdx.x == 0) s_atom = 0;
   __syncthreads();
+  const unsigned long long np = c->n_pack;
   lb_walk(w.nlist, w.nwork, pk_cnt(np), pk_work(np), w.off, w.col, nullptr, [&](Items &it) {
-    unsigned conf = 0;
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
-      if (it.vert >> k & 1) {
-        w.state[it.v[k]] = CLUST;
-        if (cw && w.flag[it.v[k]]) {
-          w.flag[it.v[k]] = 0;
-          conf++;
-        }
-      }
-    }
-    if (cw && conf) atomicAdd(&s_conf, conf);
-    int32_t lw[IPT];
+    for (int k = 0; k < IPT; k++)
+      if (it.vert >> k & 1) hist_add(s_hist, w.hist, w.ub[it.v[k]], -1);  // the vertex leaves
+    bool un[IPT];
 #pragma unroll
-    for (int k = 0; k < IPT; k++) lw[k] = (it.edge >> k & 1) ? w.lab[it.u[k]] : 0;
+    for (int k = 0; k < IPT; k++) un[k] = (it.edge >> k & 1) && unc_bit(w.unc, it.u[k]);
     unsigned dec = 0;
 #pragma unroll
     for (int k = 0; k < IPT; k++)
-      if (lw[k] == INF) {  // still unclustered after this round
-        atomicSub(&w.resdeg[it.u[k]], 1);
+      if (un[k]) {
+        const int32_t old = atomicSub(&w.ub[it.u[k]], 1);
+        hist_add(s_hist, w.hist, old, -1);
+        hist_add(s_hist, w.hist, old - 1, 1);
         dec++;
       }
     if (dec) atomicAdd(&s_atom, dec);
   });
   __syncthreads();
-  if (cw && threadIdx.x == 0 && s_conf) atomicAdd(&c->conflicts, (unsigned long long)s_conf);
+  for (int i = threadIdx.x; i < HLDS; i += BS)
+    if (s_hist[i]) atomicAdd(&w.hist[i], s_hist[i]);
   if (threadIdx.x == 0 && s_atom) atomicAdd(&c->sum_atomics, (unsigned long long)s_atom);
 }
 
-// -------------------------------------------------------------- delta -----
+// -------------------------------------------------------------- close -----
+// One wave: record the finished round, find Delta_{i+1}, size the next round.
 
-__global__ void __launch_bounds__(BS) k_delta(Ws w) {
+__global__ void __launch_bounds__(64) k_close(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
-  const int64_t n = w.n;
-  // forget this round's scan tiles
-  const int64_t tiles = (int64_t)c->tile_counter + 1;
-  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < tiles && t < w.tstat_cap;
-       t += (int64_t)gridDim.x * BS)
-    w.tstat[t] = 0;
-  int mx = 0;
-  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS)
-    if (w.state[v] == UNCL) mx = max(mx, w.resdeg[v]);
-  mx = wave_max(mx);
-  __shared__ int s_mx[WAVES];
-  if (lane_id() == 0) s_mx[wave_id()] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int m = 0;
-    for (int i = 0; i < WAVES; i++) m = max(m, s_mx[i]);
-    if (m > 0) atomicMax(&c->delta_next, m);
-  }
-  if (!last_block(&c->fin[FIN_DELTA])) return;
-  if (threadIdx.x >= 64) return;
-  // ---- close the round (wave 0 of the last workgroup; lane 0 updates the
-  // control block, the other lanes get its values by shuffle) ----
   const long long now = (long long)wall_clock64();
   long long n_rem = 0, delta = 0, round = 0;
   int done = 0;
   float fconf = 0.f, fclaim = 0.f, feps = 0.f;
+  long long prev_delta = 0;
   if (threadIdx.x == 0) {
+    prev_delta = c->delta;
     if (c->has_round) {
+      const int phase_run = c->phase;  // phase the finished round ran in
       const bool c4 = w.algo == ALGO_C4;
       const long long centers = c4 ? pk_cnt(c->c_pack) : pk_cnt(c->a_pack);
       const long long newly = pk_cnt(c->n_pack);
@@ -523,9 +820,13 @@ __global__ void __launch_bounds__(BS) k_delta(Ws w) {
         r.t_ns = now - c->t_start;
         w.trace[c->round] = r;
       }
+      unsigned long long resc = pk_work(c->x_pack);
+      for (int j = 0; j < DITER; j++) resc += pk_work(c->r_pack[j]);
       c->sum_elect += c4 ? (unsigned long long)pk_work(c->a_pack) : 0ull;
       c->sum_claim += c4 ? (unsigned long long)pk_work(c->c_pack) : (unsigned long long)pk_work(c->a_pack);
-      c->sum_peel += (unsigned long long)pk_work(c->n_pack);
+      c->sum_rescan += resc;
+      c->sum_peel += phase_run == PHASE_EXACT ? (unsigned long long)pk_work(c->n_pack) : 0ull;
+      c->sum_atomics += (unsigned long long)newly;  // bitmap clears
       c->sum_blocked += (unsigned long long)conf;
       c->feat_conf = c->b > 0 ? (float)conf / (float)c->b : 0.f;
       c->feat_claim = c->n_start > 0 ? (float)(newly - centers) / (float)c->n_start : 0.f;
@@ -534,9 +835,17 @@ __global__ void __launch_bounds__(BS) k_delta(Ws w) {
       c->n_rem = c->n_start - newly;
       c->round += 1;
       if (c->round > w.n + 1) set_error(c, ERR_NO_PROGRESS);
+      // Delta_{i+1} (lazy search, or the exact histogram below)
+      long long d = 0;
+      if (phase_run == PHASE_LAZY) {
+        const DSearch s = dsearch(c, DITER);
+        if (s.switching) c->phase = PHASE_EXACT;
+        else d = s.delta;
+      }
+      c->delta = d;
+    } else {
+      c->delta = w.max_deg;  // Delta_0
     }
-    c->delta = c->delta_next;
-    c->delta_next = 0;
     c->has_round = 1;
     c->a_pack = c->c_pack = c->n_pack = 0;
     c->tile_counter = 0;
@@ -544,6 +853,11 @@ __global__ void __launch_bounds__(BS) k_delta(Ws w) {
     c->n_blocked = 0;
     c->n_cedges = 0;
     c->conflicts = 0;
+    for (int j = 0; j < DITER; j++) {
+      c->r_pack[j] = 0;
+      c->d_max[j] = 0;
+    }
+    c->x_pack = 0;
     if (c->n_rem <= 0 || c->error) c->done = 1;
     n_rem = c->n_rem;
     delta = c->delta;
@@ -552,6 +866,28 @@ __global__ void __launch_bounds__(BS) k_delta(Ws w) {
     fconf = c->feat_conf;
     fclaim = c->feat_claim;
     feps = c->feat_eps;
+  }
+  // exact phase: Delta = highest non-empty histogram bin, at most Delta_i
+  int exact = 0;
+  long long dprev = 0;
+  if (threadIdx.x == 0) {
+    exact = c->phase == PHASE_EXACT && c->has_round && !c->done;
+    dprev = prev_delta;
+  }
+  exact = __shfl(exact, 0, 64);
+  dprev = __shfl(dprev, 0, 64);
+  if (exact) {
+    long long found = 0;
+    for (long long top = (dprev < w.max_deg ? dprev : w.max_deg); top >= 1 && !found; top -= 64) {
+      const long long x = top - lane_id();
+      const bool nz = x >= 1 && w.hist[x] > 0;
+      const unsigned long long m = __ballot(nz);
+      if (m) found = top - (__ffsll((long long)m) - 1);
+    }
+    if (threadIdx.x == 0) {
+      c->delta = found;
+      delta = found;
+    }
   }
   n_rem = __shfl(n_rem, 0, 64);
   delta = __shfl(delta, 0, 64);
@@ -573,7 +909,6 @@ __global__ void __launch_bounds__(BS) k_delta(Ws w) {
       c->t_start = now;
     }
   }
-  if (threadIdx.x == 0) c->fin[FIN_DELTA] = 0;
 }
 
 // ----------------------------------------------------------- finalize -----
@@ -600,10 +935,10 @@ static inline unsigned grid_for(int64_t items, unsigned cap) {
   return (unsigned)g;
 }
 
-hipError_t launch_init(const Ws &w, hipStream_t s) {
+hipError_t launch_init(const Ws &w, const unsigned *lvl_init_cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_invert, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_init, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_delta, dim3(grid_for(w.n, 2048)), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_init, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w, lvl_init_cnt);
+  hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, w);
   return hipGetLastError();
 }
 
@@ -612,10 +947,20 @@ hipError_t launch_round(const Ws &w, hipStream_t s, const LaunchShape &ls) {
   if (w.algo == ALGO_C4) {
     hipLaunchKernelGGL(k_elect, dim3(ls.edge_grid), dim3(BS), 0, s, w);
     hipLaunchKernelGGL(k_classify, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_resolve, dim3(1), dim3(BS), 0, s, w);
   }
   hipLaunchKernelGGL(k_claim, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_clear, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
   hipLaunchKernelGGL(k_peel, dim3(ls.edge_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_delta, dim3(grid_for(w.n, ls.scan_grid)), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_dscan<0>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_rescan<0>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_dscan<1>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_rescan<1>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_dscan<2>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_rescan<2>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_xlist, dim3(grid_for(w.n, ls.vertex_grid)), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_xcount, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, w);
   return hipGetLastError();
 }
 

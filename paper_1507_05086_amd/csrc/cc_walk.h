@@ -8,6 +8,8 @@
 // there (load-balanced search), then reads the adjacency entry with coalesced
 // loads along the row.
 #pragma once
+#include <type_traits>
+
 #include "cc_device.h"
 
 namespace ccd {
@@ -16,6 +18,7 @@ namespace ccd {
 // bit k of `edge` is set (u[k] valid) and the first item of its row when bit
 // k of `vert` is set (rows of degree 0 own exactly one such item).
 struct Items {
+  int ent[IPT];      // row index within the tile (LDS slot), -1 if no item
   int32_t v[IPT];    // row vertex
   int32_t u[IPT];    // neighbour (edge items)
   int32_t val[IPT];  // staged per-row value (e.g. rank or lab of v)
@@ -35,13 +38,24 @@ __device__ inline int lds_upper_bound(const int64_t *a, int len, int64_t x) {
   return lo;
 }
 
+struct NoEpilogue {
+  __device__ void operator()(int, int64_t, int32_t, int32_t, int64_t) const {}
+};
+struct NoPost {
+  __device__ void operator()() const {}
+};
+
 // Calls f(Items&) once per tile in every thread of the workgroup (uniformly,
 // so f may use wave-wide operations).  `vals` (may be null) is gathered per
 // row into Items::val.  A null `list` means the rows 0..cnt-1 themselves.
-template <class F>
+// After f, ep(j, slot, v, deg, covered) runs once for every row j the tile
+// touched (slot = list index, covered = items of that row in this tile), so
+// per-row partial results kept in LDS by f can be combined across tiles; then
+// post() runs in every thread (it may use barriers).
+template <class F, class E = NoEpilogue, class P = NoPost>
 __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restrict__ work, int64_t cnt,
                         int64_t total, const int64_t *__restrict__ off, const int32_t *__restrict__ col,
-                        const int32_t *__restrict__ vals, F &&f) {
+                        const int32_t *__restrict__ vals, F &&f, E &&ep = E(), P &&post = P()) {
   __shared__ int64_t lw[TW + 1];
   __shared__ int32_t lv[TW];
   __shared__ int64_t loff[TW];
@@ -97,10 +111,12 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
       it.val[k] = 0;
       it.deg[k] = 0;
       it.pos[k] = -1;
+      it.ent[k] = -1;
       epos[k] = -1;
       if (item < send) {
         const int j = lds_upper_bound(lw, nent, item) - 1;
         const int64_t local = item - lw[j];
+        it.ent[k] = j;
         it.v[k] = lv[j];
         it.val[k] = lval[j];
         it.deg[k] = ldeg[j];
@@ -116,6 +132,15 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
     for (int k = 0; k < IPT; k++)
       if (epos[k] >= 0) it.u[k] = col[epos[k]];
     f(it);
+    if constexpr (!std::is_same<typename std::decay<E>::type, NoEpilogue>::value) {
+      __syncthreads();
+      for (int j = threadIdx.x; j < nent; j += BS) {
+        const int64_t w0 = lw[j], w1 = w0 + (ldeg[j] > 0 ? ldeg[j] : 1);
+        const int64_t lo = w0 > s ? w0 : s, hi = w1 < send ? w1 : send;
+        ep(j, ent0 + j, lv[j], ldeg[j], hi - lo);
+      }
+    }
+    if constexpr (!std::is_same<typename std::decay<P>::type, NoPost>::value) post();
     ent0 += s_next;
     __syncthreads();
   }
