@@ -54,8 +54,8 @@ struct Workspace {
   uint8_t *state = nullptr, *flag = nullptr;
   int32_t *alist = nullptr, *clist = nullptr, *nlist = nullptr, *blist = nullptr;
   int64_t *awork = nullptr, *cwork = nullptr, *nwork = nullptr;
-  int32_t *rlist = nullptr, *xlist = nullptr;
-  int64_t *rwork = nullptr, *xwork = nullptr;
+  int32_t *rlist = nullptr, *xlist = nullptr, *plist = nullptr;
+  int64_t *rwork = nullptr, *xwork = nullptr, *pwork = nullptr;
   unsigned long long *racc = nullptr;
   int64_t rcap = 0;
   int32_t *lvl = nullptr;
@@ -72,7 +72,7 @@ struct Workspace {
   int64_t *sched = nullptr;
   int64_t sched_cap = 0;
   float *mlp = nullptr;
-  int *host_flags = nullptr;  // pinned: done, error
+  int *host_flags = nullptr;  // pinned: done, error, has_round, fallback, phase
   int32_t *cost_size = nullptr;
   long long *cost_acc = nullptr;
   int *dev_err = nullptr;
@@ -104,7 +104,7 @@ namespace {
 
 void free_ws(Workspace &w) {
   void *ptrs[] = {w.rank, w.lab, w.ub, w.unc, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
-                  w.awork, w.cwork, w.nwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist,
+                  w.awork, w.cwork, w.nwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist, w.plist, w.pwork,
                   w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf, w.label_buf, w.sched, w.mlp,
                   w.cost_size, w.cost_acc, w.dev_err};
   for (void *p : ptrs)
@@ -152,6 +152,8 @@ int32_t ensure_ws(cc_graph *g) {
   HIP_TRY(dalloc(&w.racc, (size_t)(DITER * w.rcap)));
   HIP_TRY(dalloc(&w.xlist, n));
   HIP_TRY(dalloc(&w.xwork, n));
+  HIP_TRY(dalloc(&w.plist, n));
+  HIP_TRY(dalloc(&w.pwork, n));
   HIP_TRY(dalloc(&w.lvl, (size_t)(g->lvl_total > 0 ? g->lvl_total : 1)));
   w.hist_len = g->max_deg + 2;
   HIP_TRY(dalloc(&w.hist, (size_t)w.hist_len));
@@ -169,7 +171,7 @@ int32_t ensure_ws(cc_graph *g) {
   HIP_TRY(dalloc(&w.cost_size, n));
   HIP_TRY(dalloc(&w.cost_acc, 2 * (size_t)g->num_graphs));
   HIP_TRY(dalloc(&w.dev_err, 1));
-  HIP_TRY(hipHostMalloc((void **)&w.host_flags, 4 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void **)&w.host_flags, 8 * sizeof(int), hipHostMallocDefault));
   w.ready = true;
   return CC_OK;
 }
@@ -253,6 +255,8 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.rcap = ws.rcap;
   w.xlist = ws.xlist;
   w.xwork = ws.xwork;
+  w.plist = ws.plist;
+  w.pwork = ws.pwork;
   w.lvl = ws.lvl;
   w.lvl_off = g->lvl_off;
   w.hist = ws.hist;
@@ -286,7 +290,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     return fail(CC_ERR_NOT_PERMUTATION, "order is not a permutation of 0..n-1");
   if (ws.host_flags[1]) return fail(CC_ERR_DEVICE, "device error during initialisation");
 
-  LaunchShape ls{256, 2048, 1024, 2048};
+  LaunchShape ls{256, 2048, 1024, 0, 0};
   int64_t launched = 0, group = 4;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   HIP_TRY(hipEventCreate(&ev0));
@@ -302,9 +306,10 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   for (;;) {
     for (int64_t r = 0; r < group; r++) HIP_TRY(launch_round(w, s, ls));
     launched += group;
-    HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->done, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (ws.host_flags[0] || ws.host_flags[1]) break;
+    if (ws.host_flags[4] == PHASE_EXACT) ls.exact_seen = 1;
     if (launched > n + 2) return fail(CC_ERR_NO_PROGRESS, "round loop exceeded n+1 rounds");
     group = group < 64 ? group * 2 : 64;
   }

@@ -25,7 +25,8 @@ constexpr int WAVES = BS / 64;
 constexpr int IPT = 4;              // adjacency items per thread per tile
 constexpr int TW = BS * IPT;        // adjacency items per tile
 constexpr int SIPT = 16;            // pi positions per thread in the active-set scan
-constexpr int TSEL = BS * SIPT;     // pi positions per scan tile
+constexpr int SEL_BS = 256;         // threads of an active-set scan workgroup
+constexpr int TSEL = SEL_BS * SIPT; // pi positions per scan tile
 constexpr int32_t INF = 0x7fffffff;
 
 enum : uint8_t { UNCL = 0, ACTIVE = 1, CENTER = 2, NONCENTER = 3 };
@@ -76,7 +77,7 @@ struct Ctrl {
   int pad1;
   long long t_start;       // wall clock at round start
   // per round
-  unsigned long long a_pack, c_pack, n_pack;  // active / center / newly lists
+  unsigned long long a_pack, c_pack, n_pack, p_pack;  // active / center / newly / peel lists
   unsigned int tile_counter;
   int select_done;
   unsigned int n_blocked, n_cedges;
@@ -105,8 +106,8 @@ struct Ws {
   uint32_t *unc;
   uint8_t *state, *flag;
   // lists
-  int32_t *alist, *clist, *nlist, *blist, *rlist, *xlist;
-  int64_t *awork, *cwork, *nwork, *rwork, *xwork;
+  int32_t *alist, *clist, *nlist, *blist, *rlist, *xlist, *plist;
+  int64_t *awork, *cwork, *nwork, *rwork, *xwork, *pwork;
   unsigned long long *racc;  // rescan accumulators (items covered << 32 | count), DITER * rcap
   int64_t rcap;         // capacity of one pass's rescan list
   int2 *cedge;
@@ -189,15 +190,17 @@ __device__ inline int wave_max(int x) {
   return x;
 }
 
-// Workgroup exclusive scan of 64-bit values; *total receives the sum.
-// Uses `sh` (WAVES+1 slots of shared memory); contains two barriers.
+// Workgroup exclusive scan of 64-bit values for NT threads; *total receives
+// the sum.  Uses `sh` (NT/64 + 1 slots of shared memory); two barriers.
+template <int NT = BS>
 __device__ inline int64_t wg_excl_scan(int64_t x, int64_t *total, int64_t *sh) {
+  constexpr int NW = NT / 64;
   const int64_t inc = wave_incl_scan(x);
   if (lane_id() == 63) sh[wave_id()] = inc;
   __syncthreads();
   int64_t base = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < WAVES; w++) {
+  for (int w = 0; w < NW; w++) {
     if (w < wave_id()) base += sh[w];
     tot += sh[w];
   }
@@ -248,5 +251,65 @@ __device__ inline int64_t wave_find_entry(const int64_t *work, int64_t cnt, int6
 }
 
 __device__ inline bool unc_bit(const uint32_t *unc, int32_t v) { return (unc[v >> 5] >> (v & 31)) & 1u; }
+
+}  // namespace ccd
+
+namespace ccd {
+
+// Workgroup-staged appends to a packed list: threads push (vertex, weight)
+// into LDS; a flush reserves the whole batch with one atomic on the list
+// counter and writes it out with coalesced stores.  Same-address device
+// atomics serialise, so this keeps them to one per flush instead of one per
+// wave and item group.
+template <int CAP>
+struct StageBuf {
+  int32_t id[CAP];
+  int32_t wt[CAP];
+  int cnt;
+  unsigned long long base;
+  int64_t sh[WAVES + 1];
+};
+
+template <int CAP>
+__device__ inline void stage_init(StageBuf<CAP> &b) {
+  if (threadIdx.x == 0) b.cnt = 0;
+  __syncthreads();
+}
+
+template <int CAP>
+__device__ inline void stage_push(StageBuf<CAP> &b, int32_t v, int32_t weight) {
+  const int p = atomicAdd(&b.cnt, 1);
+  b.id[p] = v;
+  b.wt[p] = weight;
+}
+
+// Collective: every thread of the workgroup calls it.
+template <int CAP>
+__device__ inline void stage_flush(StageBuf<CAP> &b, unsigned long long *packc, int32_t *list, int64_t *work,
+                                   unsigned long long *zero_acc = nullptr) {
+  __syncthreads();
+  const int cnt = b.cnt;
+  if (cnt == 0) return;
+  constexpr int PER = (CAP + BS - 1) / BS;
+  const int i0 = threadIdx.x * PER;
+  int64_t s = 0;
+  for (int i = i0; i < i0 + PER && i < cnt; i++) s += b.wt[i];
+  int64_t tot;
+  int64_t pre = wg_excl_scan(s, &tot, b.sh);
+  if (threadIdx.x == 0) b.base = atomicAdd(packc, pk(tot, cnt));
+  __syncthreads();
+  const int64_t slot0 = pk_cnt(b.base), w0 = pk_work(b.base);
+  for (int i = i0; i < i0 + PER && i < cnt; i++) {
+    work[slot0 + i] = w0 + pre;
+    pre += b.wt[i];
+  }
+  for (int i = threadIdx.x; i < cnt; i += BS) {
+    list[slot0 + i] = b.id[i];
+    if (zero_acc) zero_acc[slot0 + i] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) b.cnt = 0;
+  __syncthreads();
+}
 
 }  // namespace ccd

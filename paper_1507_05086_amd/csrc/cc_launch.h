@@ -10,7 +10,8 @@ struct LaunchShape {
   unsigned select_grid;  // workgroups of the active-set scan
   unsigned edge_grid;    // workgroups of the edge-balanced passes
   unsigned vertex_grid;  // workgroups of per-vertex list passes
-  unsigned scan_grid;    // cap on workgroups of the full-vertex delta scan
+  unsigned scan_grid;    // unused
+  int exact_seen;        // the host saw the run switch to exact degrees
 };
 
 hipError_t launch_init(const Ws &w, const unsigned *lvl_init_cnt, hipStream_t s);

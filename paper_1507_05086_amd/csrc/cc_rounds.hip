@@ -46,22 +46,22 @@ __device__ inline bool row_combine(unsigned long long *acc, int64_t slot, int cn
 
 // ------------------------------------------------------------------ init --
 
+// rank = order^-1 by a plain scatter; k_init checks order[rank[v]] == v for
+// every v, which fails for a missing (hence also for a repeated) vertex.
 __global__ void __launch_bounds__(BS) k_invert(Ws w) {
   const int64_t n = w.n;
   for (int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x; k < n; k += (int64_t)gridDim.x * BS) {
     const int32_t v = w.order[k];
-    if (v < 0 || (int64_t)v >= n) {
-      set_error(w.ctrl, ERR_PERM);
-      continue;
-    }
-    const int32_t old = atomicExch(&w.rank[v], (int32_t)k);
-    if (old != -1) set_error(w.ctrl, ERR_PERM);
+    if (v < 0 || (int64_t)v >= n) set_error(w.ctrl, ERR_PERM);
+    else w.rank[v] = (int32_t)k;
   }
 }
 
 __global__ void __launch_bounds__(BS) k_init(Ws w, const unsigned *lvl_init_cnt) {
   const int64_t n = w.n;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
+    const int32_t r = w.rank[v];
+    if (r < 0 || (int64_t)r >= n || w.order[r] != (int32_t)v) set_error(w.ctrl, ERR_PERM);
     w.lab[v] = INF;
     w.state[v] = UNCL;
     w.flag[v] = 0;
@@ -208,41 +208,25 @@ __global__ void __launch_bounds__(BS) k_dscan(Ws w) {
     tot += cnt < cap ? cnt : cap;
   }
   base[kT + 1] = tot;
-  int32_t *rl = w.rlist + IT * w.rcap;
-  int64_t *rw = w.rwork + IT * w.rcap;
-  unsigned long long *ra = w.racc + IT * w.rcap;
-  for (int64_t i0 = (int64_t)blockIdx.x * BS; i0 < tot; i0 += (int64_t)gridDim.x * BS) {
+  __shared__ StageBuf<2 * BS> sb;
+  stage_init(sb);
+  // a contiguous share of the entries per workgroup
+  const int64_t per = ((tot + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
+  const int64_t e0 = (int64_t)blockIdx.x * per, e1 = e0 + per < tot ? e0 + per : tot;
+  for (int64_t i0 = e0; i0 < e1; i0 += BS) {
     const int64_t i = i0 + threadIdx.x;
-    int32_t v = 0;
-    bool take = false;
-    if (i < tot) {
+    if (i < e1) {
       int k = kL;
       while (k < kT && i >= base[k + 1]) k++;
-      v = w.lvl[w.lvl_off[k] + (i - base[k])];
+      const int32_t v = w.lvl[w.lvl_off[k] + (i - base[k])];
       const int32_t x = w.ub[v];
-      take = x >= s.L && level_of(x) == k && unc_bit(w.unc, v);  // live entry, inside the band
+      if (x >= s.L && level_of(x) == k && unc_bit(w.unc, v))  // live entry, inside the band
+        stage_push(sb, v, (int32_t)(w.off[v + 1] - w.off[v]));
     }
-    const unsigned long long m = __ballot(take);
-    if (m) {
-      const int64_t d = take ? (w.off[v + 1] - w.off[v]) : 0;
-      const int64_t winc = wave_incl_scan(d);
-      const int64_t wtot = __shfl(winc, 63, 64);
-      const int leader = __ffsll((long long)m) - 1;
-      unsigned long long b0 = 0;
-      if (lane_id() == leader) b0 = atomicAdd(&c->r_pack[IT], pk(wtot, __popcll(m)));
-      b0 = __shfl(b0, leader, 64);
-      if (take) {
-        const int64_t slot = pk_cnt(b0) + __popcll(m & lanemask_lt());
-        if (slot < w.rcap) {
-          rl[slot] = v;
-          rw[slot] = pk_work(b0) + winc - d;
-          ra[slot] = 0;
-        } else {
-          set_error(c, ERR_OVERFLOW);
-        }
-      }
-    }
+    __syncthreads();
+    if (sb.cnt > BS) stage_flush(sb, &c->r_pack[IT], w.rlist + IT * w.rcap, w.rwork + IT * w.rcap, w.racc + IT * w.rcap);
   }
+  stage_flush(sb, &c->r_pack[IT], w.rlist + IT * w.rcap, w.rwork + IT * w.rcap, w.racc + IT * w.rcap);
 }
 
 // Exact remaining degrees of the pass's candidates; the new bounds move
@@ -326,31 +310,21 @@ __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
   const DSearch s = dsearch(c, DITER);
   if (!s.switching) return;
   unsigned long long *xacc = (unsigned long long *)w.awork;
+  __shared__ StageBuf<2 * BS> sb;
+  stage_init(sb);
   const int64_t n = w.n;
-  for (int64_t v0 = (int64_t)blockIdx.x * BS; v0 < n; v0 += (int64_t)gridDim.x * BS) {
-    const int64_t v = v0 + threadIdx.x;
-    bool take = false;
-    int64_t d = 0;
-    if (v < n && unc_bit(w.unc, (int32_t)v)) {
-      d = w.off[v + 1] - w.off[v];
-      take = d > 0;
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
+  const int64_t v0 = (int64_t)blockIdx.x * per, v1 = v0 + per < n ? v0 + per : n;
+  for (int64_t vb = v0; vb < v1; vb += BS) {
+    const int64_t v = vb + threadIdx.x;
+    if (v < v1 && unc_bit(w.unc, (int32_t)v)) {
+      const int64_t d = w.off[v + 1] - w.off[v];
+      if (d > 0) stage_push(sb, (int32_t)v, (int32_t)d);
     }
-    const unsigned long long m = __ballot(take);
-    if (m) {
-      const int64_t winc = wave_incl_scan(d * take);
-      const int64_t wtot = __shfl(winc, 63, 64);
-      const int leader = __ffsll((long long)m) - 1;
-      unsigned long long b0 = 0;
-      if (lane_id() == leader) b0 = atomicAdd(&c->x_pack, pk(wtot, __popcll(m)));
-      b0 = __shfl(b0, leader, 64);
-      if (take) {
-        const int64_t slot = pk_cnt(b0) + __popcll(m & lanemask_lt());
-        w.xlist[slot] = (int32_t)v;
-        w.xwork[slot] = pk_work(b0) + winc - d;
-        xacc[slot] = 0;
-      }
-    }
+    __syncthreads();
+    if (sb.cnt > BS) stage_flush(sb, &c->x_pack, w.xlist, w.xwork, xacc);
   }
+  stage_flush(sb, &c->x_pack, w.xlist, w.xwork, xacc);
 }
 
 // ... and count their unclustered neighbours into ub and the histogram.
@@ -394,35 +368,45 @@ __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
 // bits 61..0 = value.  Tiles are handed out in order by an atomic counter, so
 // a tile only ever waits for tiles that are already being processed.
 
+// Decoupled look-back by one wave: lane l reads the status of tile j - l, so
+// each step covers 64 predecessors; the walk stops at the nearest inclusive
+// prefix.  Called by all 64 lanes of a wave; returns the exclusive prefix.
 __device__ inline long long lookback(const Ws &w, unsigned t) {
   long long excl = 0;
   long long j = (long long)t - 1;
   unsigned spins = 0;
+  const int l = lane_id();
   while (j >= 0) {
-    const unsigned long long s = ld_acq(&w.tstat[j]);
+    const long long idx = j - l;
+    const unsigned long long s = idx >= 0 ? ld_acq(&w.tstat[idx]) : (2ull << 62);
     const unsigned flag = (unsigned)(s >> 62);
-    if (flag == 0) {
-      if (++spins > (1u << 24)) {
-        set_error(w.ctrl, ERR_NO_PROGRESS);
+    const unsigned long long incl = __ballot(flag == 2);
+    const unsigned long long notready = __ballot(flag == 0);
+    const int first = incl ? __ffsll((long long)incl) - 1 : 64;  // nearest inclusive prefix
+    const unsigned long long need = first < 63 ? ((2ull << first) - 1) : ~0ull;
+    if (notready & need) {  // a nearer predecessor has not published yet
+      if (++spins > (1u << 22)) {
+        if (l == 0) set_error(w.ctrl, ERR_NO_PROGRESS);
         return excl;
       }
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    excl += (long long)(s & ((1ull << 62) - 1));
-    if (flag == 2) break;
-    j--;
+    const long long val = (l <= first) ? (long long)(s & ((1ull << 62) - 1)) : 0;
+    excl += wave_sum(val);
+    if (first < 64) break;
+    j -= 64;
   }
   return excl;
 }
 
-__global__ void __launch_bounds__(BS) k_select(Ws w) {
+__global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
   __shared__ unsigned s_tile;
   __shared__ int s_stop;
   __shared__ long long s_excl;
-  __shared__ int64_t sh[WAVES + 1];
+  __shared__ int64_t sh[SEL_BS / 64 + 1];
   __shared__ unsigned long long s_base;
   const long long B = c->b, cur0 = c->cursor;
   const int64_t n = w.n;
@@ -458,17 +442,17 @@ __global__ void __launch_bounds__(BS) k_select(Ws w) {
       if (p < n && unc_bit(w.unc, vv[k])) un |= 1u << k;
     }
     int64_t agg;
-    const int64_t mine = wg_excl_scan(__popc(un), &agg, sh);
-    if (threadIdx.x == 0) {
+    const int64_t mine = wg_excl_scan<SEL_BS>(__popc(un), &agg, sh);
+    if (threadIdx.x < 64) {  // wave 0 publishes and looks back
       long long excl = 0;
       if (t == 0) {
-        st_rel(&w.tstat[0], (2ull << 62) | (unsigned long long)agg);
+        if (threadIdx.x == 0) st_rel(&w.tstat[0], (2ull << 62) | (unsigned long long)agg);
       } else {
-        st_rel(&w.tstat[t], (1ull << 62) | (unsigned long long)agg);
+        if (threadIdx.x == 0) st_rel(&w.tstat[t], (1ull << 62) | (unsigned long long)agg);
         excl = lookback(w, t);
-        st_rel(&w.tstat[t], (2ull << 62) | (unsigned long long)(excl + agg));
+        if (threadIdx.x == 0) st_rel(&w.tstat[t], (2ull << 62) | (unsigned long long)(excl + agg));
       }
-      s_excl = excl;
+      if (threadIdx.x == 0) s_excl = excl;
     }
     __syncthreads();
     const long long excl = s_excl;
@@ -476,14 +460,17 @@ __global__ void __launch_bounds__(BS) k_select(Ws w) {
     int64_t wsum = 0;
     int cnt = 0;
     unsigned act = 0;
+    int32_t wt[SIPT];
     long long r = excl + mine;
 #pragma unroll
     for (int k = 0; k < SIPT; k++) {
+      wt[k] = 0;
       if (un & (1u << k)) {
         if (r < B) {
           act |= 1u << k;
           cnt++;
-          wsum += row_weight(w.off, vv[k]);
+          wt[k] = (int32_t)row_weight(w.off, vv[k]);
+          wsum += wt[k];
           if (r == B - 1) {
             c->r_last = base + k;
             st_rel(&c->select_done, 1);
@@ -493,8 +480,8 @@ __global__ void __launch_bounds__(BS) k_select(Ws w) {
       }
     }
     int64_t wtot, ctot;
-    const int64_t wpre = wg_excl_scan(wsum, &wtot, sh);
-    const int64_t cpre = wg_excl_scan(cnt, &ctot, sh);
+    const int64_t wpre = wg_excl_scan<SEL_BS>(wsum, &wtot, sh);
+    const int64_t cpre = wg_excl_scan<SEL_BS>(cnt, &ctot, sh);
     if (threadIdx.x == 0 && ctot > 0) s_base = atomicAdd(&c->a_pack, pk(wtot, ctot));
     __syncthreads();
     if (ctot > 0) {
@@ -508,7 +495,7 @@ __global__ void __launch_bounds__(BS) k_select(Ws w) {
           w.alist[slot] = v;
           w.awork[slot] = wpos;
           slot++;
-          wpos += row_weight(w.off, v);
+          wpos += wt[k];
         }
       }
     }
@@ -552,22 +539,25 @@ __global__ void __launch_bounds__(BS) k_elect(Ws w) {
 __global__ void __launch_bounds__(BS) k_classify(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
+  __shared__ StageBuf<2 * BS> sb;
+  stage_init(sb);
   const int64_t na = pk_cnt(c->a_pack);
-  for (int64_t i0 = (int64_t)blockIdx.x * BS; i0 < na; i0 += (int64_t)gridDim.x * BS) {
-    const int64_t i = i0 + threadIdx.x;
+  const int64_t per = ((na + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
+  const int64_t a0 = (int64_t)blockIdx.x * per, a1 = a0 + per < na ? a0 + per : na;
+  for (int64_t ib = a0; ib < a1; ib += BS) {
+    const int64_t i = ib + threadIdx.x;
     int32_t a = 0;
-    bool blocked = false, root = false;
-    if (i < na) {
+    bool blocked = false;
+    if (i < a1) {
       a = w.alist[i];
       blocked = w.flag[a] != 0;
-      root = !blocked;
+      if (!blocked) {
+        w.state[a] = CENTER;
+        w.lab[a] = w.rank[a];
+        stage_push(sb, a, (int32_t)row_weight(w.off, a));
+      }
     }
-    if (root) {
-      w.state[a] = CENTER;
-      w.lab[a] = w.rank[a];
-    }
-    wave_append(root, a, root ? row_weight(w.off, a) : 0, &c->c_pack, w.clist, w.cwork);
-    const unsigned long long m = __ballot(blocked);
+    const unsigned long long m = __ballot(blocked);  // blocked vertices are rare
     if (m) {
       const int leader = __ffsll((long long)m) - 1;
       unsigned base = 0;
@@ -575,7 +565,10 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
       base = __shfl(base, leader, 64);
       if (blocked) w.blist[base + __popcll(m & lanemask_lt())] = a;
     }
+    __syncthreads();
+    if (sb.cnt > BS) stage_flush(sb, &c->c_pack, w.clist, w.cwork);
   }
+  stage_flush(sb, &c->c_pack, w.clist, w.cwork);
 }
 
 // One workgroup: a blocked vertex is a non-center as soon as an earlier
@@ -672,6 +665,8 @@ __global__ void __launch_bounds__(BS) k_resolve(Ws w) {
 
 // -------------------------------------------------------------- claim -----
 
+constexpr int CLAIM_CAP = 3 * TW;  // staged newly-clustered entries (a tile adds <= 2*TW)
+
 __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
@@ -680,62 +675,78 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   const int32_t *list = c4 ? w.clist : w.alist;
   const int64_t *work = c4 ? w.cwork : w.awork;
   __shared__ unsigned s_atom;
+  __shared__ StageBuf<CLAIM_CAP> sb;
   if (threadIdx.x == 0) s_atom = 0;
-  __syncthreads();
-  lb_walk(list, work, pk_cnt(lp), pk_work(lp), w.off, w.col, w.rank, [&](Items &it) {
-    // every center is clustered this round
+  stage_init(sb);
+  lb_walk(
+      list, work, pk_cnt(lp), pk_work(lp), w.off, w.col, w.rank,
+      [&](Items &it) {
+        // every center is clustered this round
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
-      const bool vt = it.vert >> k & 1;
-      wave_append(vt, it.v[k], it.deg[k] > 0 ? it.deg[k] : 1, &c->n_pack, w.nlist, w.nwork);
-    }
-    bool un[IPT];
+        for (int k = 0; k < IPT; k++)
+          if (it.vert >> k & 1) stage_push(sb, it.v[k], it.deg[k] > 0 ? it.deg[k] : 1);
+        bool un[IPT];
 #pragma unroll
-    for (int k = 0; k < IPT; k++) un[k] = (it.edge >> k & 1) && unc_bit(w.unc, it.u[k]);
-    bool elig[IPT];
-    int32_t cur[IPT];
+        for (int k = 0; k < IPT; k++) un[k] = (it.edge >> k & 1) && unc_bit(w.unc, it.u[k]);
+        bool elig[IPT];
+        int32_t cur[IPT];
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
-      elig[k] = un[k];
-      if (!c4 && un[k] && w.state[it.u[k]] == ACTIVE) {  // ClusterWild! claims Gamma(c) \ A
-        elig[k] = false;
-        if (w.rank[it.u[k]] < it.val[k]) w.flag[it.v[k]] = 1;  // rule 1 broken
-      }
-      cur[k] = elig[k] ? w.lab[it.u[k]] : 0;  // stale reads are safe: labels only decrease
-    }
+        for (int k = 0; k < IPT; k++) {
+          elig[k] = un[k];
+          if (!c4 && un[k] && w.state[it.u[k]] == ACTIVE) {  // ClusterWild! claims Gamma(c) \ A
+            elig[k] = false;
+            if (w.rank[it.u[k]] < it.val[k]) w.flag[it.v[k]] = 1;  // rule 1 broken
+          }
+          cur[k] = elig[k] ? w.lab[it.u[k]] : 0;  // stale reads are safe: labels only decrease
+        }
+        unsigned atom = 0;
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
-      bool first = false;
-      int64_t wt = 0;
-      if (elig[k] && it.val[k] < cur[k]) {
-        const int32_t old = atomicMin(&w.lab[it.u[k]], it.val[k]);
-        atomicAdd(&s_atom, 1u);
-        first = (old == INF);
-        if (first) wt = row_weight(w.off, it.u[k]);
-      }
-      wave_append(first, it.u[k], wt, &c->n_pack, w.nlist, w.nwork);
-    }
-  });
-  __syncthreads();
+        for (int k = 0; k < IPT; k++) {
+          if (elig[k] && it.val[k] < cur[k]) {
+            const int32_t old = atomicMin(&w.lab[it.u[k]], it.val[k]);
+            atom++;
+            if (old == INF) stage_push(sb, it.u[k], (int32_t)row_weight(w.off, it.u[k]));
+          }
+        }
+        if (atom) atomicAdd(&s_atom, atom);
+      },
+      NoEpilogue(),
+      [&]() {
+        __syncthreads();
+        if (sb.cnt > CLAIM_CAP - 2 * TW) stage_flush(sb, &c->n_pack, w.nlist, w.nwork);
+      });
+  stage_flush(sb, &c->n_pack, w.nlist, w.nwork);
   if (threadIdx.x == 0 && s_atom) atomicAdd(&c->sum_atomics, (unsigned long long)s_atom);
 }
 
-// The newly clustered leave the unclustered bitmap; ClusterWild! conflict
-// marks are counted; the scan tiles of this round are forgotten.
+// The newly clustered leave the unclustered bitmap; in the exact phase those
+// that still had unclustered neighbours go to the peel list; ClusterWild!
+// conflict marks are counted; the scan tiles of this round are forgotten.
 __global__ void __launch_bounds__(BS) k_clear(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
+  __shared__ StageBuf<2 * BS> sp;
+  stage_init(sp);
   const int64_t nn = pk_cnt(c->n_pack);
-  const bool cw = w.algo == ALGO_CW;
+  const bool cw = w.algo == ALGO_CW, exact = c->phase == PHASE_EXACT;
   unsigned conf = 0;
-  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < nn; i += (int64_t)gridDim.x * BS) {
-    const int32_t u = w.nlist[i];
-    atomicAnd(&w.unc[u >> 5], ~(1u << (u & 31)));
-    if (cw && w.flag[u]) {
-      w.flag[u] = 0;
-      conf++;
+  const int64_t per = ((nn + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
+  const int64_t i0 = (int64_t)blockIdx.x * per, i1 = i0 + per < nn ? i0 + per : nn;
+  for (int64_t ib = i0; ib < i1; ib += BS) {
+    const int64_t i = ib + threadIdx.x;
+    if (i < i1) {
+      const int32_t u = w.nlist[i];
+      atomicAnd(&w.unc[u >> 5], ~(1u << (u & 31)));
+      if (cw && w.flag[u]) {
+        w.flag[u] = 0;
+        conf++;
+      }
+      if (exact && w.ub[u] > 0) stage_push(sp, u, (int32_t)(w.off[u + 1] - w.off[u]));
     }
+    __syncthreads();
+    if (sp.cnt > BS) stage_flush(sp, &c->p_pack, w.plist, w.pwork);
   }
+  stage_flush(sp, &c->p_pack, w.plist, w.pwork);
   const int64_t tiles = (int64_t)c->tile_counter + 1;
   for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < tiles && t < w.tstat_cap;
        t += (int64_t)gridDim.x * BS)
@@ -763,8 +774,8 @@ __global__ void __launch_bounds__(BS) k_peel(Ws w) {
   for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
   if (threadIdx.x == 0) s_atom = 0;
   __syncthreads();
-  const unsigned long long np = c->n_pack;
-  lb_walk(w.nlist, w.nwork, pk_cnt(np), pk_work(np), w.off, w.col, nullptr, [&](Items &it) {
+  const unsigned long long pp = c->p_pack;
+  lb_walk(w.plist, w.pwork, pk_cnt(pp), pk_work(pp), w.off, w.col, nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++)
       if (it.vert >> k & 1) hist_add(s_hist, w.hist, w.ub[it.v[k]], -1);  // the vertex leaves
@@ -825,7 +836,7 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
       c->sum_elect += c4 ? (unsigned long long)pk_work(c->a_pack) : 0ull;
       c->sum_claim += c4 ? (unsigned long long)pk_work(c->c_pack) : (unsigned long long)pk_work(c->a_pack);
       c->sum_rescan += resc;
-      c->sum_peel += phase_run == PHASE_EXACT ? (unsigned long long)pk_work(c->n_pack) : 0ull;
+      c->sum_peel += phase_run == PHASE_EXACT ? (unsigned long long)pk_work(c->p_pack) : 0ull;
       c->sum_atomics += (unsigned long long)newly;  // bitmap clears
       c->sum_blocked += (unsigned long long)conf;
       c->feat_conf = c->b > 0 ? (float)conf / (float)c->b : 0.f;
@@ -847,7 +858,7 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
       c->delta = w.max_deg;  // Delta_0
     }
     c->has_round = 1;
-    c->a_pack = c->c_pack = c->n_pack = 0;
+    c->a_pack = c->c_pack = c->n_pack = c->p_pack = 0;
     c->tile_counter = 0;
     c->select_done = 0;
     c->n_blocked = 0;
@@ -943,7 +954,7 @@ hipError_t launch_init(const Ws &w, const unsigned *lvl_init_cnt, hipStream_t s)
 }
 
 hipError_t launch_round(const Ws &w, hipStream_t s, const LaunchShape &ls) {
-  hipLaunchKernelGGL(k_select, dim3(ls.select_grid), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_select, dim3(ls.select_grid), dim3(SEL_BS), 0, s, w);
   if (w.algo == ALGO_C4) {
     hipLaunchKernelGGL(k_elect, dim3(ls.edge_grid), dim3(BS), 0, s, w);
     hipLaunchKernelGGL(k_classify, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
@@ -951,15 +962,20 @@ hipError_t launch_round(const Ws &w, hipStream_t s, const LaunchShape &ls) {
   }
   hipLaunchKernelGGL(k_claim, dim3(ls.edge_grid), dim3(BS), 0, s, w);
   hipLaunchKernelGGL(k_clear, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_peel, dim3(ls.edge_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_dscan<0>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_rescan<0>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_dscan<1>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_rescan<1>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_dscan<2>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_rescan<2>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_xlist, dim3(grid_for(w.n, ls.vertex_grid)), dim3(BS), 0, s, w);
-  hipLaunchKernelGGL(k_xcount, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+  if (ls.exact_seen) {
+    // the run has switched to exact degrees for good: no lazy search
+    hipLaunchKernelGGL(k_peel, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+  } else {
+    hipLaunchKernelGGL(k_peel, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_dscan<0>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_rescan<0>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_dscan<1>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_rescan<1>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_dscan<2>, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_rescan<2>, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_xlist, dim3(grid_for(w.n, ls.vertex_grid)), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_xcount, dim3(ls.edge_grid), dim3(BS), 0, s, w);
+  }
   hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, w);
   return hipGetLastError();
 }
