@@ -240,4 +240,10 @@ def workload(name: str) -> Graph:
     if name.startswith("rmat"):
         scale = int(name[4:])
         return rmat(scale, 16, 0.57, 0.19, 0.19, seed=3 if scale == 26 else 100 + scale)
+    if name.startswith("sbm"):
+        # planted blocks: lognormal sizes (median 500) clipped to [50, 5000],
+        # 2-40 blocks, p_in = 0.3, p_out = 0.01
+        count = int(name[3:])
+        sizes, blocks = sbm_shapes(count, seed=4)
+        return sbm_batch(sizes, blocks, 0.3, 0.01, seed=4)
     raise KeyError(name)

@@ -97,6 +97,8 @@ typedef struct cc_run_stats {
   int32_t truncated;       /* out: 1 if more rounds ran than trace_capacity */
   cc_round_record *trace;  /* in: host buffer of trace_capacity records, or NULL */
   int64_t trace_capacity;  /* in */
+  int32_t *graph_rounds;   /* in: host int32[num_graphs] receiving each graph's rounds
+                              (batches; rounds then holds their maximum), or NULL */
 } cc_run_stats;
 
 /*
@@ -154,6 +156,46 @@ CC_API int32_t cc_c4(const cc_graph *g, const int32_t *order, double eps, int32_
  */
 CC_API int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double eps, int32_t *labels,
                        cc_run_stats *stats, uint32_t flags, void *stream);
+
+/*
+ * Batches (num_graphs > 1).  cc_c4 and cc_clusterwild cluster every graph of
+ * a batch in ONE persistent kernel launch: a group of threads takes a graph
+ * from a queue (largest first), keeps its vertex state in LDS and runs the
+ * whole round loop of Algorithm 2 on it with the fixed eps rule, then takes
+ * the next graph.  Graphs of at most `wave_max_n` vertices run on a single
+ * wave (several per workgroup); larger ones on a whole workgroup of `block`
+ * threads.  Each graph may hold at most CC_BATCH_MAX_N vertices (the LDS of
+ * one workgroup).  Labels are per graph, local ids; per-graph rounds come
+ * back in cc_run_stats.graph_rounds; no per-round trace is recorded.  A
+ * batch run with a LEARNED or TRACE policy set fails with CC_ERR_POLICY.
+ */
+#define CC_BATCH_MAX_N 7680
+enum cc_algo { CC_ALGO_C4 = 0, CC_ALGO_CLUSTERWILD = 1 };
+
+typedef struct cc_batch_config {
+  int32_t block;      /* threads per workgroup: 256, 512 or 1024 */
+  int32_t wave_max_n; /* graphs with n_g <= wave_max_n run one per wave (0: none) */
+  double ms;          /* cc_batch_autotune: best measured time of one launch */
+} cc_batch_config;
+
+/*
+ * Fix the launch shape of a batch handle (cfg->ms is ignored).  Without a
+ * call, a handle uses the shape cc_batch_autotune last chose for a batch of
+ * the same size class (number of graphs, largest and median graph, rounded
+ * up to powers of two, and the device) in this process, else a built-in
+ * default.  CC_ERR_INVALID_ARG if the shape does not fit the device's LDS.
+ */
+CC_API int32_t cc_batch_set_config(cc_graph *g, const cc_batch_config *cfg);
+
+/*
+ * Time every launch shape that fits (block in {256, 512, 1024} x a ladder of
+ * wave_max_n values) on this batch with `algo` (cc_algo), `order` and `eps`
+ * (as for cc_c4; flags: CC_INPUT_ON_DEVICE only), keep the fastest for the
+ * handle and for its size class, and return it in *best (may be NULL).
+ * Runs the batch three times per shape; labels are not returned.
+ */
+CC_API int32_t cc_batch_autotune(cc_graph *g, int32_t algo, const int32_t *order, double eps,
+                                 uint32_t flags, void *stream, cc_batch_config *best);
 
 /*
  * Disagreements of a clustering (the objective of Section 2):

@@ -43,8 +43,12 @@ CC_EPS_TRACE = 2
 CC_MLP_IN, CC_MLP_HIDDEN = 6, 64
 CC_MLP_PARAMS = CC_MLP_HIDDEN * CC_MLP_IN + CC_MLP_HIDDEN + CC_MLP_HIDDEN + 1
 
+CC_ALGO_C4, CC_ALGO_CLUSTERWILD = 0, 1
+CC_BATCH_MAX_N = 7680
+
 ABI_FUNCTIONS = ("cc_graph_from_csr", "cc_graph_destroy", "cc_graph_info", "cc_c4",
-                 "cc_clusterwild", "cc_cost", "cc_set_eps_policy", "cc_last_error")
+                 "cc_clusterwild", "cc_cost", "cc_batch_set_config", "cc_batch_autotune",
+                 "cc_set_eps_policy", "cc_last_error")
 
 TRACE_FIELDS = ("n_i", "delta_i", "b_i", "r_i", "centers", "claimed", "conflicts", "eps_used", "t_ns")
 
@@ -68,7 +72,11 @@ class _RunStats(ctypes.Structure):
                 ("blocked", ctypes.c_int64), ("atomics", ctypes.c_int64),
                 ("loop_ms", ctypes.c_double), ("policy_fallback", ctypes.c_int32),
                 ("truncated", ctypes.c_int32), ("trace", ctypes.POINTER(_RoundRecord)),
-                ("trace_capacity", ctypes.c_int64)]
+                ("trace_capacity", ctypes.c_int64), ("graph_rounds", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("wave_max_n", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 def _load():
@@ -84,6 +92,8 @@ def _load():
         "cc_c4": ([vp, vp, f64, vp, ctypes.POINTER(_RunStats), u32, vp], i32),
         "cc_clusterwild": ([vp, vp, f64, vp, ctypes.POINTER(_RunStats), u32, vp], i32),
         "cc_cost": ([vp, vp, vp, u32, vp], i32),
+        "cc_batch_set_config": ([vp, ctypes.POINTER(_BatchConfig)], i32),
+        "cc_batch_autotune": ([vp, i32, vp, f64, u32, vp, ctypes.POINTER(_BatchConfig)], i32),
         "cc_set_eps_policy": ([i32, vp, ctypes.c_size_t, f64, f64], i32),
         "cc_last_error": ([], ctypes.c_char_p),
     }
@@ -195,6 +205,7 @@ class RunStats:
     policy_fallback: int = 0
     truncated: int = 0
     trace: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    graph_rounds: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
 
 
 def _run(fn, graph: Graph, order, eps, labels=None, trace_capacity=1 << 14, stream=None):
@@ -213,12 +224,14 @@ def _run(fn, graph: Graph, order, eps, labels=None, trace_capacity=1 << 14, stre
         rec = (_RoundRecord * trace_capacity)()
         st.trace = ctypes.cast(rec, ctypes.POINTER(_RoundRecord))
         st.trace_capacity = trace_capacity
+    gr = np.zeros(max(graph.num_graphs, 1), dtype=np.int32)
+    st.graph_rounds = gr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     _check(fn(graph.handle, po, float(eps), pl, ctypes.byref(st), flags, _stream(stream, order, labels)))
     out = RunStats(rounds=st.rounds, scanned_elect=st.scanned_elect, scanned_claim=st.scanned_claim,
                    scanned_peel=st.scanned_peel, scanned_delta=st.scanned_delta, blocked=st.blocked,
                    atomics=st.atomics,
                    loop_ms=st.loop_ms, policy_fallback=st.policy_fallback,
-                   truncated=st.truncated)
+                   truncated=st.truncated, graph_rounds=gr)
     if rec is not None:
         k = min(st.rounds, trace_capacity)
         dt = np.dtype([(f, np.float64 if f == "eps_used" else np.int64) for f in TRACE_FIELDS])
@@ -245,6 +258,29 @@ def cc_cost(graph: Graph, labels, stream=None) -> np.ndarray:
     _check(_lib.cc_cost(graph.handle, pl, ctypes.c_void_p(out.ctypes.data),
                         CC_INPUT_ON_DEVICE if ldev else 0, _stream(stream, labels)))
     return out
+
+
+@dataclass
+class BatchConfig:
+    block: int
+    wave_max_n: int
+    ms: float = 0.0
+
+
+def cc_batch_set_config(graph: Graph, block: int, wave_max_n: int):
+    """Fix a batch's launch shape: `block` threads per workgroup, graphs of at
+    most `wave_max_n` vertices one per wave."""
+    c = _BatchConfig(int(block), int(wave_max_n), 0.0)
+    _check(_lib.cc_batch_set_config(graph.handle, ctypes.byref(c)))
+
+
+def cc_batch_autotune(graph: Graph, order, algo: int = CC_ALGO_C4, eps: float = 0.5, stream=None) -> BatchConfig:
+    """Time every launch shape that fits on this batch and keep the fastest."""
+    po, odev, _ko = _ptr(order, np.int32)
+    c = _BatchConfig()
+    _check(_lib.cc_batch_autotune(graph.handle, int(algo), po, float(eps), CC_INPUT_ON_DEVICE if odev else 0,
+                                  _stream(stream, order), ctypes.byref(c)))
+    return BatchConfig(c.block, c.wave_max_n, c.ms)
 
 
 def cc_set_eps_policy(kind: int, params=None, eps_min: float = 1.0 / 16, eps_max: float = 16.0):

@@ -2,11 +2,14 @@
 // the host side of the round loop, statistics and traces.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/cc.h"
@@ -78,6 +81,24 @@ struct Workspace {
   int *dev_err = nullptr;
 };
 
+// Device buffers and launch shape of a batch.
+struct BatchState {
+  int32_t *queue = nullptr;
+  unsigned *heads = nullptr;
+  int32_t *rounds = nullptr;
+  unsigned long long *stat = nullptr;
+  int *err = nullptr;
+  int q_block = 0, q_wave = -1;  // shape the uploaded queue was built for
+  int n_big = 0, cap_big = 0, cap_wave = 0;
+  bool has_cfg = false;          // shape fixed by cc_batch_set_config / cc_batch_autotune
+  cc_batch_config cfg{};
+};
+
+// Size class of a batch: log2 buckets of (graphs, largest graph, median graph).
+using SizeClass = std::tuple<int, int, int, int>;
+std::map<SizeClass, cc_batch_config> g_tuned;
+std::mutex g_tuned_mu;
+
 }  // namespace
 
 struct cc_graph {
@@ -98,6 +119,7 @@ struct cc_graph {
   std::vector<int64_t> h_vtx_ptr;
   std::vector<int64_t> m_per_graph;
   Workspace ws;
+  BatchState bs;
 };
 
 namespace {
@@ -116,6 +138,12 @@ void free_ws(Workspace &w) {
 void free_graph(cc_graph *g) {
   if (!g) return;
   free_ws(g->ws);
+  {
+    BatchState &b = g->bs;
+    void *ptrs[] = {b.queue, b.heads, b.rounds, b.stat, b.err};
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+  }
   if (!g->borrowed) {
     if (g->off) (void)hipFree(g->off);
     if (g->col) (void)hipFree(g->col);
@@ -184,6 +212,9 @@ int32_t wall_clock_khz(int *khz) {
   return CC_OK;
 }
 
+int32_t run_batch(cc_graph *g, int algo, const int32_t *order, double eps, int32_t *labels, cc_run_stats *stats,
+                  uint32_t flags, hipStream_t s);
+
 int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_t *labels,
                  cc_run_stats *stats, uint32_t flags, hipStream_t s) {
   if (!g) return fail(CC_ERR_INVALID_ARG, "graph handle is NULL");
@@ -194,8 +225,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     return fail(CC_ERR_INVALID_ARG, "unknown flag for a run");
   if (stats && stats->trace_capacity > 0 && !stats->trace)
     return fail(CC_ERR_INVALID_ARG, "stats->trace is NULL but trace_capacity > 0");
-  if (g->num_graphs != 1)
-    return fail(CC_ERR_INVALID_ARG, "batched graphs are clustered by the batched entry points");
+  if (g->num_graphs != 1) return run_batch(g, algo, order, eps, labels, stats, flags, s);
   Policy pol;
   {
     std::lock_guard<std::mutex> lk(g_policy_mu);
@@ -207,7 +237,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   if (n == 0) {
     if (stats) {
       std::memset(stats, 0, offsetof(cc_run_stats, trace));
-      stats->truncated = 0;
+      if (stats->graph_rounds) stats->graph_rounds[0] = 0;
     }
     return CC_OK;
   }
@@ -332,6 +362,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   }
   if (stats) {
     stats->rounds = hc.round;
+    if (stats->graph_rounds) stats->graph_rounds[0] = (int32_t)hc.round;
     stats->scanned_elect = (int64_t)hc.sum_elect;
     stats->scanned_claim = (int64_t)hc.sum_claim;
     stats->scanned_peel = (int64_t)hc.sum_peel;
@@ -365,6 +396,279 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
       }
     }
   }
+  return CC_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+int ilog2_ceil(int64_t x) {
+  int k = 0;
+  while (((int64_t)1 << k) < x) k++;
+  return k;
+}
+
+int64_t graph_n(const cc_graph *g, int32_t i) { return g->h_vtx_ptr[(size_t)i + 1] - g->h_vtx_ptr[(size_t)i]; }
+
+int32_t device_arch(int *arch_id, int *max_lds) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t p;
+  HIP_TRY(hipGetDeviceProperties(&p, dev));
+  *arch_id = p.major * 100 + p.minor * 10;
+  *max_lds = (int)p.sharedMemPerBlock;
+  return CC_OK;
+}
+
+SizeClass size_class(const cc_graph *g, int arch) {
+  std::vector<int64_t> ns((size_t)g->num_graphs);
+  for (int32_t i = 0; i < g->num_graphs; i++) ns[(size_t)i] = graph_n(g, i);
+  std::sort(ns.begin(), ns.end());
+  const int64_t mx = ns.empty() ? 0 : ns.back(), med = ns.empty() ? 0 : ns[ns.size() / 2];
+  return SizeClass{arch, ilog2_ceil(g->num_graphs), ilog2_ceil(mx + 1), ilog2_ceil(med + 1)};
+}
+
+// LDS (bytes of dynamic shared memory) a shape needs for this batch; sets the
+// slot capacities: the largest graph of each queue.
+size_t shape_lds(const cc_graph *g, int block, int wave_max_n, int *cap_big, int *cap_wave, int *n_big) {
+  int cb = 0, cw = 0, nb = 0;
+  for (int32_t i = 0; i < g->num_graphs; i++) {
+    const int n = (int)graph_n(g, i);
+    if (n > wave_max_n) {
+      cb = std::max(cb, n);
+      nb++;
+    } else {
+      cw = std::max(cw, n);
+    }
+  }
+  if (cap_big) *cap_big = cb;
+  if (cap_wave) *cap_wave = cw;
+  if (n_big) *n_big = nb;
+  return batched_lds_bytes(block, cb, cw);
+}
+
+// Static LDS of the batched kernel (graph id + scan scratch), with slack.
+constexpr int kBatchStaticLds = 512;
+
+int32_t check_shape(const cc_graph *g, const cc_batch_config &c) {
+  if (c.block != 256 && c.block != 512 && c.block != 1024)
+    return fail(CC_ERR_INVALID_ARG, "batch block must be 256, 512 or 1024");
+  if (c.wave_max_n < 0) return fail(CC_ERR_INVALID_ARG, "wave_max_n must be >= 0");
+  int arch = 0, max_lds = 0;
+  if (int32_t rc = device_arch(&arch, &max_lds)) return rc;
+  const size_t lds = shape_lds(g, c.block, c.wave_max_n, nullptr, nullptr, nullptr);
+  if (lds + kBatchStaticLds > (size_t)max_lds)
+    return fail(CC_ERR_INVALID_ARG, "batch shape needs " + std::to_string(lds) + " B of LDS per workgroup; the device has " +
+                                        std::to_string(max_lds));
+  return CC_OK;
+}
+
+cc_batch_config default_shape(const cc_graph *g) {
+  // one wave per graph while four wave slots fit beside the largest graph's slot
+  cc_batch_config c{256, 0, 0.0};
+  int64_t mx = 0;
+  for (int32_t i = 0; i < g->num_graphs; i++) mx = std::max(mx, graph_n(g, i));
+  c.wave_max_n = (int)std::min<int64_t>(512, std::max<int64_t>(64, mx / 4));
+  return c;
+}
+
+int32_t ensure_batch(cc_graph *g) {
+  BatchState &b = g->bs;
+  if (b.queue) return CC_OK;
+  HIP_TRY(dalloc(&b.queue, (size_t)g->num_graphs));
+  HIP_TRY(dalloc(&b.heads, 2));
+  HIP_TRY(dalloc(&b.rounds, (size_t)g->num_graphs));
+  HIP_TRY(dalloc(&b.stat, 4));
+  HIP_TRY(dalloc(&b.err, 1));
+  return CC_OK;
+}
+
+// Queue of graph ids: graphs above wave_max_n first, then the rest; each part
+// in decreasing order of work (entries + vertices), so the persistent groups
+// finish together (longest-processing-time-first).
+int32_t build_queue(cc_graph *g, int block, int wave_max_n, hipStream_t s) {
+  BatchState &b = g->bs;
+  if (b.q_block == block && b.q_wave == wave_max_n) return CC_OK;
+  std::vector<int32_t> big, small;
+  for (int32_t i = 0; i < g->num_graphs; i++) (graph_n(g, i) > wave_max_n ? big : small).push_back(i);
+  auto work = [&](int32_t i) { return 2 * g->m_per_graph[(size_t)i] + graph_n(g, i); };
+  auto by_work = [&](int32_t x, int32_t y) { return work(x) != work(y) ? work(x) > work(y) : x < y; };
+  std::sort(big.begin(), big.end(), by_work);
+  std::sort(small.begin(), small.end(), by_work);
+  std::vector<int32_t> q(big);
+  q.insert(q.end(), small.begin(), small.end());
+  HIP_TRY(hipMemcpyAsync(b.queue, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  shape_lds(g, block, wave_max_n, &b.cap_big, &b.cap_wave, &b.n_big);
+  b.q_block = block;
+  b.q_wave = wave_max_n;
+  return CC_OK;
+}
+
+// One launch over the whole batch; d_order and d_labels are device buffers.
+int32_t launch_batch(cc_graph *g, int algo, const int32_t *d_order, int64_t eps_q, int32_t *d_labels,
+                     const cc_batch_config &c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  BatchState &b = g->bs;
+  if (int32_t rc = build_queue(g, c.block, c.wave_max_n, s)) return rc;
+  const size_t lds = batched_lds_bytes(c.block, b.cap_big, b.cap_wave);
+  int grid = 0;
+  HIP_TRY(batched_max_grid(c.block, lds, &grid));
+  if (grid < 1) return fail(CC_ERR_DEVICE, "batched kernel does not fit on a compute unit");
+  const int waves = c.block / 64;
+  const int64_t nsmall = g->num_graphs - b.n_big;
+  const int64_t need = std::max<int64_t>(1, b.n_big + (nsmall + waves - 1) / waves);
+  if (need < grid) grid = (int)need;
+  HIP_TRY(hipMemsetAsync(b.heads, 0, 2 * sizeof(unsigned), s));
+  HIP_TRY(hipMemsetAsync(b.stat, 0, 4 * sizeof(unsigned long long), s));
+  HIP_TRY(hipMemsetAsync(b.err, 0, sizeof(int), s));
+  BatchLaunch bl{g->off, g->col, g->vtx_ptr, d_order, d_labels, b.queue, b.n_big, g->num_graphs, b.cap_big,
+                 b.cap_wave, b.heads, b.rounds, b.stat, b.err, algo, eps_q, c.block, grid};
+  if (ev0) HIP_TRY(hipEventRecord(ev0, s));
+  HIP_TRY(launch_batched(bl, s));
+  if (ev1) HIP_TRY(hipEventRecord(ev1, s));
+  return CC_OK;
+}
+
+int32_t batch_error(int e) {
+  if (e == ERR_PERM) return fail(CC_ERR_NOT_PERMUTATION, "order of a graph is not a permutation of 0..n_g-1");
+  if (e == ERR_NO_PROGRESS) return fail(CC_ERR_NO_PROGRESS, "a graph's round loop made no progress");
+  return fail(CC_ERR_DEVICE, "device error " + std::to_string(e) + " in the batched loop");
+}
+
+int32_t batch_prepare(cc_graph *g, const int32_t *order, double eps, uint32_t flags, hipStream_t s,
+                      const int32_t **d_order, int64_t *eps_q) {
+  if (!(eps > 0.0) || !(eps <= 1000.0) || !std::isfinite(eps))
+    return fail(CC_ERR_INVALID_ARG, "eps must lie in (0, 1000]");
+  {
+    std::lock_guard<std::mutex> lk(g_policy_mu);
+    if (g_policy.kind != CC_EPS_FIXED)
+      return fail(CC_ERR_POLICY, "batches use the fixed eps rule; set CC_EPS_FIXED first");
+  }
+  for (int32_t i = 0; i < g->num_graphs; i++)
+    if (graph_n(g, i) > CC_BATCH_MAX_N)
+      return fail(CC_ERR_INVALID_ARG, "graph " + std::to_string(i) + " of the batch has more than CC_BATCH_MAX_N vertices");
+  if (int32_t rc = ensure_ws(g)) return rc;
+  if (int32_t rc = ensure_batch(g)) return rc;
+  *d_order = order;
+  if (!(flags & CC_INPUT_ON_DEVICE)) {
+    HIP_TRY(hipMemcpyAsync(g->ws.order_buf, order, sizeof(int32_t) * (size_t)g->n, hipMemcpyHostToDevice, s));
+    *d_order = g->ws.order_buf;
+  }
+  *eps_q = (int64_t)(eps * 1e6 + 0.5);
+  return CC_OK;
+}
+
+int32_t run_batch(cc_graph *g, int algo, const int32_t *order, double eps, int32_t *labels, cc_run_stats *stats,
+                  uint32_t flags, hipStream_t s) {
+  const int32_t *d_order = nullptr;
+  int64_t eps_q = 0;
+  if (int32_t rc = batch_prepare(g, order, eps, flags, s, &d_order, &eps_q)) return rc;
+  BatchState &b = g->bs;
+  cc_batch_config c = b.cfg;
+  if (!b.has_cfg) {
+    int arch = 0, max_lds = 0;
+    if (int32_t rc = device_arch(&arch, &max_lds)) return rc;
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned.find(size_class(g, arch));
+    c = it != g_tuned.end() ? it->second : default_shape(g);
+  }
+  if (int32_t rc = check_shape(g, c)) return rc;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  HIP_TRY(hipEventCreate(&ev0));
+  HIP_TRY(hipEventCreate(&ev1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{ev0, ev1};
+  // labels go to the workspace first, so a failing graph leaves the caller's untouched
+  if (int32_t rc = launch_batch(g, algo, d_order, eps_q, g->ws.label_buf, c, s, ev0, ev1)) return rc;
+  int herr = 0;
+  unsigned long long hst[4];
+  HIP_TRY(hipMemcpyAsync(&herr, b.err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hst, b.stat, sizeof(hst), hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> rounds((size_t)g->num_graphs);
+  HIP_TRY(hipMemcpyAsync(rounds.data(), b.rounds, sizeof(int32_t) * rounds.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (herr) return batch_error(herr);
+  HIP_TRY(hipMemcpyAsync(labels, g->ws.label_buf, sizeof(int32_t) * (size_t)g->n,
+                         (flags & CC_OUTPUT_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (stats) {
+    int64_t mx = 0;
+    for (int32_t r : rounds) mx = std::max<int64_t>(mx, r);
+    stats->rounds = mx;
+    stats->scanned_elect = (int64_t)hst[0];
+    stats->scanned_claim = (int64_t)hst[1];
+    stats->scanned_peel = (int64_t)hst[2];
+    stats->scanned_delta = 0;
+    stats->blocked = 0;
+    stats->atomics = (int64_t)hst[3];
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+    stats->loop_ms = ms;
+    stats->policy_fallback = 0;
+    stats->truncated = 0;
+    if (stats->graph_rounds) std::memcpy(stats->graph_rounds, rounds.data(), sizeof(int32_t) * rounds.size());
+  }
+  return CC_OK;
+}
+
+int32_t autotune_batch(cc_graph *g, int algo, const int32_t *order, double eps, uint32_t flags, hipStream_t s,
+                       cc_batch_config *best) {
+  const int32_t *d_order = nullptr;
+  int64_t eps_q = 0;
+  if (int32_t rc = batch_prepare(g, order, eps, flags, s, &d_order, &eps_q)) return rc;
+  int arch = 0, max_lds = 0;
+  if (int32_t rc = device_arch(&arch, &max_lds)) return rc;
+  int64_t mx = 0;
+  for (int32_t i = 0; i < g->num_graphs; i++) mx = std::max(mx, graph_n(g, i));
+  static const int kWave[] = {0, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 7680};
+  static const int kBlock[] = {256, 512, 1024};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  HIP_TRY(hipEventCreate(&ev0));
+  HIP_TRY(hipEventCreate(&ev1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{ev0, ev1};
+  cc_batch_config top{0, 0, 1e300};
+  for (int blk : kBlock) {
+    int prev_cap = -1;
+    for (int wv : kWave) {
+      if (wv > 0 && wv / 2 >= mx) break;  // every graph already runs on a wave
+      cc_batch_config c{blk, wv, 0.0};
+      int cb = 0, cw = 0, nb = 0;
+      const size_t lds = shape_lds(g, blk, wv, &cb, &cw, &nb);
+      if (lds + kBatchStaticLds > (size_t)max_lds) continue;
+      if (cw == prev_cap) continue;  // same split as the previous rung
+      prev_cap = cw;
+      double t = 1e300;
+      for (int rep = 0; rep < 3; rep++) {
+        if (int32_t rc = launch_batch(g, algo, d_order, eps_q, g->ws.label_buf, c, s, ev0, ev1)) return rc;
+        int herr = 0;
+        HIP_TRY(hipMemcpyAsync(&herr, g->bs.err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (herr) return batch_error(herr);
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+        if (rep > 0) t = std::min(t, (double)ms);  // first run warms caches
+      }
+      if (t < top.ms) top = cc_batch_config{blk, wv, t};
+    }
+  }
+  if (top.block == 0) return fail(CC_ERR_INVALID_ARG, "no batch shape fits the device's LDS");
+  g->bs.cfg = top;
+  g->bs.has_cfg = true;
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned[size_class(g, arch)] = top;
+  }
+  if (best) *best = top;
   return CC_OK;
 }
 
@@ -577,6 +881,27 @@ int32_t cc_cost(const cc_graph *gc, const int32_t *labels, int64_t *cost, uint32
   for (int32_t i = 0; i < g->num_graphs; i++)
     cost[i] = (int64_t)acc[2 * (size_t)i] + g->m_per_graph[(size_t)i] - (int64_t)acc[2 * (size_t)i + 1];
   return CC_OK;
+}
+
+int32_t cc_batch_set_config(cc_graph *g, const cc_batch_config *cfg) {
+  g_last_error.clear();
+  if (!g || !cfg) return fail(CC_ERR_INVALID_ARG, "graph handle and cfg must not be NULL");
+  if (g->num_graphs < 2) return fail(CC_ERR_INVALID_ARG, "not a batch (num_graphs < 2)");
+  if (int32_t rc = check_shape(g, *cfg)) return rc;
+  g->bs.cfg = *cfg;
+  g->bs.cfg.ms = 0.0;
+  g->bs.has_cfg = true;
+  return CC_OK;
+}
+
+int32_t cc_batch_autotune(cc_graph *g, int32_t algo, const int32_t *order, double eps, uint32_t flags, void *stream,
+                          cc_batch_config *best) {
+  g_last_error.clear();
+  if (!g || !order) return fail(CC_ERR_INVALID_ARG, "graph handle and order must not be NULL");
+  if (g->num_graphs < 2) return fail(CC_ERR_INVALID_ARG, "not a batch (num_graphs < 2)");
+  if (algo != CC_ALGO_C4 && algo != CC_ALGO_CLUSTERWILD) return fail(CC_ERR_INVALID_ARG, "unknown algorithm");
+  if (flags & ~(uint32_t)CC_INPUT_ON_DEVICE) return fail(CC_ERR_INVALID_ARG, "unknown flag for cc_batch_autotune");
+  return autotune_batch(g, algo, order, eps, flags, (hipStream_t)stream, best);
 }
 
 int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes, double eps_min, double eps_max) {

@@ -33,6 +33,27 @@ hipError_t launch_level_count(const int64_t *off, int64_t n, unsigned *count, in
 hipError_t launch_level_fill(const int64_t *off, int64_t n, const int64_t *lvl_off, unsigned *cursor,
                              int32_t *lvl, hipStream_t s);
 
+// Batched C4 / ClusterWild!: one persistent launch over many small graphs.
+struct BatchLaunch {
+  const int64_t *off;
+  const int32_t *col;
+  const int64_t *vtx_ptr;
+  const int32_t *order;
+  int32_t *labels;
+  const int32_t *queue;
+  int32_t n_big, num_graphs, cap_big, cap_wave;
+  unsigned *heads;
+  int32_t *rounds;
+  unsigned long long *stat;
+  int *err;
+  int algo;
+  int64_t eps_q;
+  int block, grid;
+};
+hipError_t launch_batched(const BatchLaunch &bl, hipStream_t s);
+size_t batched_lds_bytes(int block, int cap_big, int cap_wave);
+hipError_t batched_max_grid(int block, size_t lds, int *grid);
+
 // Disagreement cost per graph: acc[2g] = pairs inside clusters, acc[2g+1] =
 // same-label adjacency entries (2 m_in); size is scratch [n].
 hipError_t launch_cost(const int64_t *off, const int32_t *col, const int64_t *wall, int64_t n,
