@@ -169,7 +169,7 @@ CC_API int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double ep
  * back in cc_run_stats.graph_rounds; no per-round trace is recorded.  A
  * batch run with a LEARNED or TRACE policy set fails with CC_ERR_POLICY.
  */
-#define CC_BATCH_MAX_N 7680
+#define CC_BATCH_MAX_N 7168
 enum cc_algo { CC_ALGO_C4 = 0, CC_ALGO_CLUSTERWILD = 1 };
 
 typedef struct cc_batch_config {

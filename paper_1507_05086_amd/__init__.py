@@ -44,7 +44,7 @@ CC_MLP_IN, CC_MLP_HIDDEN = 6, 64
 CC_MLP_PARAMS = CC_MLP_HIDDEN * CC_MLP_IN + CC_MLP_HIDDEN + CC_MLP_HIDDEN + 1
 
 CC_ALGO_C4, CC_ALGO_CLUSTERWILD = 0, 1
-CC_BATCH_MAX_N = 7680
+CC_BATCH_MAX_N = 7168
 
 ABI_FUNCTIONS = ("cc_graph_from_csr", "cc_graph_destroy", "cc_graph_info", "cc_c4",
                  "cc_clusterwild", "cc_cost", "cc_batch_set_config", "cc_batch_autotune",

@@ -446,8 +446,9 @@ size_t shape_lds(const cc_graph *g, int block, int wave_max_n, int *cap_big, int
   return batched_lds_bytes(block, cb, cw);
 }
 
-// Static LDS of the batched kernel (graph id + scan scratch), with slack.
-constexpr int kBatchStaticLds = 512;
+// Static LDS of the batched kernel (graph id, scan scratch, 256 B of window
+// scratch per wave), with slack.
+constexpr int kBatchStaticLds = 4608;
 
 int32_t check_shape(const cc_graph *g, const cc_batch_config &c) {
   if (c.block != 256 && c.block != 512 && c.block != 1024)
@@ -624,7 +625,7 @@ int32_t autotune_batch(cc_graph *g, int algo, const int32_t *order, double eps, 
   if (int32_t rc = device_arch(&arch, &max_lds)) return rc;
   int64_t mx = 0;
   for (int32_t i = 0; i < g->num_graphs; i++) mx = std::max(mx, graph_n(g, i));
-  static const int kWave[] = {0, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 7680};
+  static const int kWave[] = {0, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 7168};
   static const int kBlock[] = {256, 512, 1024};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   HIP_TRY(hipEventCreate(&ev0));

@@ -4,18 +4,25 @@
 // A graph of a few thousand vertices fits in LDS, so the whole round loop of
 // one graph runs inside one group of threads with its vertex state in LDS:
 // a workgroup for large graphs, a single wave for small ones (several graphs
-// per workgroup).  Groups take graphs from two queues (large first, largest
-// graph first), so the launch is balanced by longest-processing-time order.
+// per workgroup).  Groups take graphs from two queues (large first, most work
+// first), so the launch is balanced by longest-processing-time order.
 // Inside a graph the remaining degrees are kept exactly (LDS atomics are
-// cheap), every adjacency pass is edge-balanced over the group through a
-// prefix of row lengths in LDS, and the C4 election is the same wait-free
-// fixed point as the single-graph path.
+// cheap), and the adjacency passes (election, claims, peeling) are
+// edge-balanced: each wave walks a contiguous range of the concatenated rows,
+// streaming long rows with several loads in flight and locating row
+// boundaries inside mixed windows with one LDS scatter and a wave scan.
 #include "cc_device.h"
 #include "cc_launch.h"
 
 namespace ccd {
 
-enum : uint8_t { F_UNC = 1, F_ACT = 2, F_CEN = 4, F_NON = 8, F_BLK = 16 };
+enum : uint8_t { F_UNC = 1, F_ACT = 2, F_CEN = 4, F_NON = 8, F_BLK = 16, F_MC = 32, F_MU = 64 };
+
+// Packed per-vertex word: clusterID (rank of the center, INF16 while
+// unclustered) in the high half, remaining positive degree in the low half.
+// Ranks and degrees of a batch member are below 2^15.
+constexpr uint32_t INF16 = 0x7FFF;
+__device__ inline uint32_t lw_pack(uint32_t lab, uint32_t deg) { return (lab << 16) | deg; }
 
 // A group of G threads working on one graph (G = 64: one wave; G = block).
 template <int G>
@@ -57,6 +64,12 @@ struct Grp {
   __device__ bool any(bool p) const { return max(p ? 1 : 0) != 0; }
 };
 
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct BStats {
   unsigned long long elect, claim, peel, atom;
 };
@@ -67,7 +80,7 @@ struct BatchArgs {
   const int64_t *vtx_ptr;  // [num_graphs + 1]
   const int32_t *order;    // per graph local permutation (concatenated)
   int32_t *labels;         // out: local center ids
-  const int32_t *queue;    // graph ids, large-graph queue first, each part largest first
+  const int32_t *queue;    // graph ids, large-graph queue first, each part most work first
   int32_t n_big;           // queue[0, n_big): one graph per workgroup; rest: one per wave
   int32_t num_graphs;
   int32_t cap_big, cap_wave;  // LDS vertex capacity of a workgroup slot / a wave slot
@@ -79,23 +92,35 @@ struct BatchArgs {
   int64_t eps_q;
 };
 
-// LDS slot of capacity N vertices: 21 bytes per vertex plus a counter.
+// LDS slot of capacity N vertices (21 bytes per vertex plus a few words):
+//   lw     packed clusterID | remaining degree
+//   pref   [N+1] prefix of row lengths of the list being walked
+//   rstart [N+1] start of each row in the graph's cols
+//   ctr    list counter
+//   fl     flag byte, padded to whole words (word atomics touch 4 flags)
+//   rank   pi^-1 (int16)
+//   ordl   pi, position -> vertex (int16)
+//   alist  active vertices; compacted in place to the centers
+//   nlist  undecided actives during the election, then the newly clustered
 struct Slot {
-  int32_t *lab, *rdeg, *pref;
-  int16_t *rank, *alist, *clist, *nlist;
-  uint8_t *fl;
+  uint32_t *lw;
+  int32_t *pref, *rstart;
   int *ctr;
-  __host__ __device__ static size_t bytes(int N) { return (((size_t)N * 21 + 4 + 15) / 16) * 16; }
+  uint8_t *fl;
+  int16_t *rank, *ordl, *alist, *nlist;
+  __host__ __device__ static size_t bytes(int N) {
+    return (((size_t)N * 20 + 12 + (((size_t)N + 3) & ~(size_t)3)) + 15) / 16 * 16;
+  }
   __device__ void carve(uint8_t *p, int N) {
-    lab = (int32_t *)p;
-    rdeg = lab + N;
-    pref = rdeg + N;
-    rank = (int16_t *)(pref + N);
-    alist = rank + N;
-    clist = alist + N;
-    nlist = clist + N;
-    fl = (uint8_t *)(nlist + N);
-    ctr = (int *)(p + (((size_t)N * 21 + 3) / 4) * 4);
+    lw = (uint32_t *)p;
+    pref = (int32_t *)(lw + N);
+    rstart = pref + N + 1;
+    ctr = rstart + N + 1;
+    fl = (uint8_t *)(ctr + 1);
+    rank = (int16_t *)(fl + ((N + 3) & ~3));
+    ordl = rank + N;
+    alist = ordl + N;
+    nlist = alist + N;
   }
 };
 
@@ -109,38 +134,125 @@ __device__ inline long long bt_batch(long long eps_q, long long n_rem, long long
 }
 
 // Edge-balanced pass over the rows of list[0..cnt): f(i, v, u) for every
-// entry u of row v = list[i].  Row lengths are prefix-summed into pref.
-template <int G, class F>
-__device__ inline int64_t rows_pass(const Grp<G> &g, const int16_t *list, int cnt, int32_t *pref,
-                                    const int64_t *off, const int32_t *col, F &&f) {
-  int64_t carry = 0;
+// entry u of row v = list[i]; row v is col0[rstart[v] .. rstart[v+1]).  `rs`
+// is the calling wave's 64 ints of LDS scratch.  Each wave walks a contiguous
+// range of the concatenated rows: a row covering the next 64 or more entries
+// is streamed with K loads in flight; otherwise up to W windows of 64 entries
+// have their rows located (LDS only) before their loads are issued together.
+// Returns the number of entries walked.
+template <int G, int K, int W, class F>
+__device__ __forceinline__ int rows_pass(const Grp<G> &g, const int16_t *list, int cnt, Slot &s, const int32_t *col0,
+                                int *rs, F &&f) {
+  int carry = 0;
   for (int i0 = 0; i0 < cnt; i0 += G) {
     const int i = i0 + g.tid;
-    const int64_t d = i < cnt ? off[list[i] + 1] - off[list[i]] : 0;
+    int d = 0;
+    if (i < cnt) {
+      const int32_t v = list[i];
+      d = s.rstart[v + 1] - s.rstart[v];
+    }
     int64_t tot;
-    const int64_t pre = g.scan(d, &tot);
-    if (i < cnt) pref[i] = (int32_t)(carry + pre);
-    carry += tot;
+    const int pre = (int)g.scan(d, &tot);
+    if (i < cnt) s.pref[i] = carry + pre;
+    carry += (int)tot;
   }
+  const int total = carry;
+  if (g.tid == 0) s.pref[cnt] = total;
   g.sync();
-  const int64_t total = carry;
-  for (int64_t e = g.tid; e < total; e += G) {
-    int lo = 0, hi = cnt;  // last i with pref[i] <= e
+  if (total == 0) return 0;
+  constexpr int NW = G / 64;
+  const int lane = lane_id();
+  const int w = NW == 1 ? 0 : wave_id();
+  int chunk = (total + NW - 1) / NW;
+  chunk = (chunk + 63) & ~63;
+  const int c0 = min(total, w * chunk), c1 = min(total, c0 + chunk);
+  if (c0 < c1) {
+    // lo: the last row whose prefix is <= c0 (the same search in every lane)
+    int lo = 0, hi = cnt;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (pref[mid] <= e) lo = mid;
+      if (s.pref[mid] <= c0) lo = mid;
       else hi = mid;
     }
-    const int32_t v = list[lo];
-    const int32_t u = col[off[v] + (e - pref[lo])];
-    f(lo, v, u);
+    // invariant: pref[lo] <= e0 <= pref[lo + 1] and lo < cnt
+    int e0 = c0;
+    while (e0 < c1) {
+      const int b0 = s.pref[lo + 1];
+      if (b0 >= e0 + 64) {
+        // row lo covers the next 64 or more entries: stream them
+        const int end = min(b0, c1);
+        const int32_t v = list[lo];
+        const int32_t *cp = col0 + (s.rstart[v] - s.pref[lo]);
+        for (int e = e0 + lane; e < end; e += 64 * K) {
+          int32_t u[K];
+#pragma unroll
+          for (int k = 0; k < K; k++) u[k] = e + 64 * k < end ? cp[e + 64 * k] : -1;
+#pragma unroll
+          for (int k = 0; k < K; k++)
+            if (u[k] >= 0) f(lo, v, u[k]);
+        }
+        e0 = end;
+        if (e0 == b0) lo++;
+        continue;
+      }
+      // up to W windows [e0, e0 + 64) holding row starts: the row of entry
+      // e0 + l is lo + #{j : pref[lo + 1 + j] <= e0 + l}
+      int rowk[W], ek[W];
+#pragma unroll
+      for (int k = 0; k < W; k++) {
+        rowk[k] = -1;
+        ek[k] = -1;
+        if (e0 >= c1 || (k > 0 && s.pref[lo + 1] >= e0 + 64)) continue;  // uniform
+        const int j = lo + 1 + lane;
+        const int bj = j <= cnt ? s.pref[j] : 0x7fffffff;
+        const bool in = bj <= e0 + 63;
+        const bool full = __ballot(in) == ~0ull;
+        int wend = full ? __shfl(bj, 63, 64) : e0 + 64;
+        if (wend > c1) wend = c1;
+        rs[lane] = 0;
+        wave_sync();
+        const int bn = __shfl_down(bj, 1, 64);
+        if (in && (lane == 63 || bn != bj)) rs[bj - e0] = lane + 1;
+        wave_sync();
+        int r = rs[lane];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int t = __shfl_up(r, d, 64);
+          if (lane >= d) r = t > r ? t : r;
+        }
+        if (e0 + lane < wend) {
+          rowk[k] = lo + r;
+          ek[k] = e0 + lane;
+        }
+        lo += __popcll(__ballot(bj <= wend));
+        e0 = wend;
+        wave_sync();
+      }
+      int32_t vk[W], ck[W], uk[W];
+#pragma unroll
+      for (int k = 0; k < W; k++) {
+        vk[k] = 0;
+        ck[k] = 0;
+        if (rowk[k] >= 0) {
+          vk[k] = list[rowk[k]];
+          ck[k] = s.rstart[vk[k]] + (ek[k] - s.pref[rowk[k]]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < W; k++) uk[k] = rowk[k] >= 0 ? col0[ck[k]] : -1;
+#pragma unroll
+      for (int k = 0; k < W; k++)
+        if (rowk[k] >= 0) f(rowk[k], vk[k], uk[k]);
+    }
   }
   g.sync();
   return total;
 }
 
+// Inlined into the kernel so that every Slot pointer is known to address LDS
+// (an out-of-line call would turn them into generic pointers).
 template <int G>
-__device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap, Slot &s, BStats &st) {
+__device__ __forceinline__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap, Slot &s, int *rs, BStats &st) {
   const int64_t v0 = a.vtx_ptr[gi];
   const int n = (int)(a.vtx_ptr[gi + 1] - v0);
   if (n > cap) {  // the host sizes the slots; never taken
@@ -148,27 +260,33 @@ __device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap
     return;
   }
   const int64_t *off = a.off + v0;
-  const int32_t *col = a.col;
+  const int64_t obase = off[0];
+  const int32_t *col0 = a.col + obase;
   const int32_t *ord = a.order + v0;
   const bool c4 = a.algo == ALGO_C4;
-  // init; rank = ord^-1 with a permutation check
-  for (int v = g.tid; v < n; v += G) {
-    s.lab[v] = INF;
-    s.rdeg[v] = (int32_t)(off[v + 1] - off[v]);
-    s.fl[v] = F_UNC;
-    s.rank[v] = -1;
+  constexpr int K = 4, W = 4;
+  // init: row starts, packed words, pi in LDS; rank = pi^-1 with a permutation check
+  for (int v = g.tid; v <= n; v += G) {
+    const int64_t o = off[v];
+    s.rstart[v] = (int32_t)(o - obase);
+    if (v < n) {
+      s.lw[v] = lw_pack(INF16, (uint32_t)(off[v + 1] - o));
+      s.fl[v] = F_UNC;
+      s.rank[v] = -1;
+    }
   }
   g.sync();
   bool bad = false;
   for (int k = g.tid; k < n; k += G) {
     const int32_t v = ord[k];
+    s.ordl[k] = (int16_t)v;
     if (v < 0 || v >= n) bad = true;
     else s.rank[v] = (int16_t)k;
   }
   g.sync();
   for (int v = g.tid; v < n; v += G) {
     const int r = s.rank[v];
-    if (r < 0 || ord[r] != v) bad = true;
+    if (r < 0 || s.ordl[r] != v) bad = true;
   }
   if (g.any(bad)) {
     if (g.tid == 0) atomicCAS(a.err, 0, ERR_PERM);
@@ -178,8 +296,10 @@ __device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap
   while (n_rem > 0 && rounds <= n) {
     // Delta over the unclustered vertices
     int64_t m = 0;
-    for (int v = g.tid; v < n; v += G)
-      if ((s.fl[v] & F_UNC) && s.rdeg[v] > m) m = s.rdeg[v];
+    for (int v = g.tid; v < n; v += G) {
+      const int64_t d = (int64_t)(s.lw[v] & 0xFFFFu);
+      if ((s.fl[v] & F_UNC) && d > m) m = d;
+    }
     const long long delta = g.max(m);
     const int B = (int)bt_batch(a.eps_q, n_rem, delta);
     // active set: the next B unclustered vertices of pi from the cursor
@@ -189,7 +309,7 @@ __device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap
       int32_t v = 0;
       bool un = false;
       if (p < n) {
-        v = ord[p];
+        v = s.ordl[p];
         un = (s.fl[v] & F_UNC) != 0;
       }
       int64_t tot;
@@ -213,7 +333,7 @@ __device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap
     int nc = 0;
     if (c4) {
       // blocked: an earlier-ranked active neighbour
-      const int64_t t_elect = rows_pass(g, s.alist, B, s.pref, off, col, [&](int, int32_t av, int32_t u) {
+      const int t_elect = rows_pass<G, K, W>(g, s.alist, B, s, col0, rs, [&](int, int32_t av, int32_t u) {
         if ((s.fl[u] & F_ACT) && s.rank[u] < s.rank[av]) s.fl[av] |= F_BLK;
       });
       if (g.tid == 0) st.elect += (unsigned long long)t_elect;
@@ -222,7 +342,9 @@ __device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap
         if (!(s.fl[av] & F_BLK)) s.fl[av] |= F_CEN;
       }
       g.sync();
-      // fixed point over the blocked vertices (row rescans; blocked sets are small)
+      // fixed point over the blocked vertices: a vertex becomes a center once
+      // no earlier active neighbour is a center or undecided, and a
+      // non-center once an earlier active neighbour is a center
       for (int it = 0; it <= B; it++) {
         int nb = 0;
         for (int i0 = 0; i0 < B; i0 += G) {
@@ -239,43 +361,41 @@ __device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap
         }
         g.sync();
         if (nb == 0) break;
-        const int64_t t_res = rows_pass(g, s.nlist, nb, s.pref, off, col, [&](int, int32_t av, int32_t u) {
-          if ((s.fl[u] & F_ACT) && s.rank[u] < s.rank[av]) {
-            // marks in the two top bits of rdeg (degrees < 2^30): bit 30 = an
-            // earlier center, bit 31 = an earlier undecided vertex
-            const int bit = (s.fl[u] & F_CEN) ? 1 : ((s.fl[u] & F_NON) ? 0 : 2);
-            if (bit) atomicOr((unsigned *)&s.rdeg[av], (unsigned)bit << 30);
+        const int t_res = rows_pass<G, K, W>(g, s.nlist, nb, s, col0, rs, [&](int, int32_t av, int32_t u) {
+          const uint8_t fu = s.fl[u];
+          if ((fu & F_ACT) && s.rank[u] < s.rank[av]) {
+            const unsigned bit = (fu & F_CEN) ? (unsigned)F_MC : ((fu & F_NON) ? 0u : (unsigned)F_MU);
+            if (bit) atomicOr((unsigned *)(s.fl + (av & ~3)), bit << (8 * (av & 3)));
           }
         });
         if (g.tid == 0) st.elect += (unsigned long long)t_res;
         for (int i = g.tid; i < nb; i += G) {
           const int32_t av = s.nlist[i];
-          const unsigned mark = ((unsigned)s.rdeg[av]) >> 30;
-          s.rdeg[av] &= 0x3FFFFFFF;
-          if (mark & 1) s.fl[av] |= F_NON;
-          else if (!(mark & 2)) s.fl[av] |= F_CEN;
+          const uint8_t f = s.fl[av];
+          uint8_t nf = (uint8_t)(f & ~(F_MC | F_MU));
+          if (f & F_MC) nf |= F_NON;
+          else if (!(f & F_MU)) nf |= F_CEN;
+          s.fl[av] = nf;
         }
         g.sync();
       }
+      // compact the centers to the front of alist, in place: every write
+      // lands at or before the chunk whose entries are already read
       for (int i0 = 0; i0 < B; i0 += G) {
         const int i = i0 + g.tid;
         bool cen = false;
-        int32_t av = 0;
+        int16_t av = 0;
         if (i < B) {
           av = s.alist[i];
           cen = (s.fl[av] & F_CEN) != 0;
         }
         int64_t tot;
         const int64_t pre = g.scan(cen ? 1 : 0, &tot);
-        if (cen) s.clist[nc + pre] = (int16_t)av;
+        if (cen) s.alist[nc + pre] = av;
         nc += (int)tot;
       }
     } else {
-      for (int i = g.tid; i < B; i += G) {
-        const int32_t av = s.alist[i];
-        s.fl[av] |= F_CEN;
-        s.clist[i] = (int16_t)av;
-      }
+      for (int i = g.tid; i < B; i += G) s.fl[s.alist[i]] |= F_CEN;
       nc = B;
     }
     g.sync();
@@ -284,20 +404,20 @@ __device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap
     if (g.tid == 0) *nn_ptr = 0;
     g.sync();
     for (int i = g.tid; i < nc; i += G) {
-      const int32_t cv = s.clist[i];
-      s.lab[cv] = s.rank[cv];
+      const int32_t cv = s.alist[i];
+      s.lw[cv] = lw_pack((uint32_t)s.rank[cv], 0);
       s.nlist[atomicAdd(nn_ptr, 1)] = (int16_t)cv;
     }
     g.sync();
-    const int64_t t_claim = rows_pass(g, s.clist, nc, s.pref, off, col, [&](int i, int32_t cv, int32_t u) {
+    const int t_claim = rows_pass<G, K, W>(g, s.alist, nc, s, col0, rs, [&](int, int32_t cv, int32_t u) {
       const uint8_t fu = s.fl[u];
       if (!(fu & F_UNC) || (fu & F_CEN)) return;
       if (!c4 && (fu & F_ACT)) return;  // ClusterWild! claims Gamma(c) \ A
-      const int32_t rc = s.rank[cv];
-      if (rc < s.lab[u]) {
-        const int32_t old = atomicMin(&s.lab[u], rc);
+      const uint32_t rc = (uint32_t)s.rank[cv];
+      if (rc < (s.lw[u] >> 16)) {
+        const uint32_t old = atomicMin(&s.lw[u], lw_pack(rc, 0xFFFFu));
         st.atom++;
-        if (old == INF) s.nlist[atomicAdd(nn_ptr, 1)] = (int16_t)u;
+        if ((old >> 16) == INF16) s.nlist[atomicAdd(nn_ptr, 1)] = (int16_t)u;
       }
     });
     if (g.tid == 0) st.claim += (unsigned long long)t_claim;
@@ -305,22 +425,21 @@ __device__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap
     // the newly clustered leave; their unclustered neighbours lose one degree
     for (int i = g.tid; i < nn; i += G) s.fl[s.nlist[i]] = 0;
     g.sync();
-    const int64_t t_peel = rows_pass(g, s.nlist, nn, s.pref, off, col, [&](int, int32_t, int32_t u) {
+    const int t_peel = rows_pass<G, K, W>(g, s.nlist, nn, s, col0, rs, [&](int, int32_t, int32_t u) {
       if (s.fl[u] & F_UNC) {
-        atomicSub(&s.rdeg[u], 1);
+        atomicSub(&s.lw[u], 1u);
         st.atom++;
       }
     });
     if (g.tid == 0) st.peel += (unsigned long long)t_peel;
-    // active marks of this round are done (every active vertex is now clustered)
     n_rem -= nn;
     rounds++;
     g.sync();
   }
   for (int v = g.tid; v < n; v += G) {
-    const int32_t l = s.lab[v];
-    a.labels[v0 + v] = (l >= 0 && l < n) ? ord[l] : -1;
-    if (l < 0 || l >= n) atomicCAS(a.err, 0, ERR_LABEL);
+    const uint32_t l = s.lw[v] >> 16;
+    a.labels[v0 + v] = l < (uint32_t)n ? (int32_t)s.ordl[l] : -1;
+    if (l >= (uint32_t)n) atomicCAS(a.err, 0, ERR_LABEL);
   }
   if (g.tid == 0) a.rounds[gi] = rounds;
   if (n_rem > 0 && g.tid == 0) atomicCAS(a.err, 0, ERR_NO_PROGRESS);
@@ -332,6 +451,8 @@ __global__ void __launch_bounds__(T) k_batched(BatchArgs a) {
   BStats st{0, 0, 0, 0};
   __shared__ int s_gi;
   __shared__ int64_t sh[T / 64 + 1];
+  __shared__ int rsb[T / 64][64];
+  int *rs = rsb[wave_id()];
   // phase 1: large graphs, one per workgroup
   Grp<T> gw{(int)threadIdx.x, sh};
   Slot sl;
@@ -345,7 +466,7 @@ __global__ void __launch_bounds__(T) k_batched(BatchArgs a) {
     const int gi = s_gi;
     __syncthreads();
     if (gi < 0) break;
-    solve_graph<T>(gw, a, gi, a.cap_big, sl, st);
+    solve_graph<T>(gw, a, gi, a.cap_big, sl, rs, st);
     __syncthreads();
   }
   // phase 2: small graphs, one per wave
@@ -358,7 +479,7 @@ __global__ void __launch_bounds__(T) k_batched(BatchArgs a) {
     if (lane_id() == 0) q = (int)atomicAdd(&a.heads[1], 1u);
     q = __shfl(q, 0, 64);
     if (q >= nsmall) break;
-    solve_graph<64>(gv, a, a.queue[a.n_big + q], a.cap_wave, sv, st);
+    solve_graph<64>(gv, a, a.queue[a.n_big + q], a.cap_wave, sv, rs, st);
   }
   // statistics: one reduction per workgroup, one atomic per counter
   __syncthreads();
