@@ -232,6 +232,29 @@ CC_API int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes
 #define CC_MLP_HIDDEN 64
 #define CC_MLP_PARAMS (CC_MLP_HIDDEN * CC_MLP_IN + CC_MLP_HIDDEN + CC_MLP_HIDDEN + 1)
 
+/*
+ * Training and batch inference of the learned policy's network (float32,
+ * parameter layout as for CC_EPS_LEARNED).  The paper fixes eps for a run;
+ * this network and its training are an addition.  All pointers are DEVICE
+ * pointers; x is float32[n][CC_MLP_IN] row-major (the per-round features of
+ * cc_set_eps_policy).  Work is queued on `stream`; the call returns after it
+ * has finished.  0 <= n < 2^31.
+ *
+ * cc_mlp_forward: y[i] = w2 . relu(W1 x_i + b1) + b2.
+ */
+CC_API int32_t cc_mlp_forward(const float *params, const float *x, int64_t n, float *y, void *stream);
+
+/*
+ * cc_mlp_train_step: the gradient of L = mean_i (y_i - target_i)^2 at
+ * `params` (backpropagation; written to grad[CC_MLP_PARAMS] unless NULL, L
+ * to *loss unless NULL), then, when lr > 0, one Adam step (beta1 = 0.9,
+ * beta2 = 0.999, eps = 1e-8, bias correction with step >= 1) that updates
+ * params, adam_m and adam_v (float32[CC_MLP_PARAMS] each; zero them before
+ * step 1).  lr == 0 computes the gradient only.
+ */
+CC_API int32_t cc_mlp_train_step(float *params, float *adam_m, float *adam_v, const float *x, const float *target,
+                                 int64_t n, int64_t step, float lr, float *grad, float *loss, void *stream);
+
 /* Text of the calling thread's last failure ("" if none). */
 CC_API const char *cc_last_error(void);
 

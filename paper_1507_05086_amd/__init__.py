@@ -48,7 +48,7 @@ CC_BATCH_MAX_N = 7168
 
 ABI_FUNCTIONS = ("cc_graph_from_csr", "cc_graph_destroy", "cc_graph_info", "cc_c4",
                  "cc_clusterwild", "cc_cost", "cc_batch_set_config", "cc_batch_autotune",
-                 "cc_set_eps_policy", "cc_last_error")
+                 "cc_mlp_forward", "cc_mlp_train_step", "cc_set_eps_policy", "cc_last_error")
 
 TRACE_FIELDS = ("n_i", "delta_i", "b_i", "r_i", "centers", "claimed", "conflicts", "eps_used", "t_ns")
 
@@ -83,6 +83,9 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_1507_05086_amd.build.build() "
                           "(hipcc, gfx950); there is no CPU fallback")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so both see the same devices, streams and memory
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
     sig = {
@@ -94,6 +97,8 @@ def _load():
         "cc_cost": ([vp, vp, vp, u32, vp], i32),
         "cc_batch_set_config": ([vp, ctypes.POINTER(_BatchConfig)], i32),
         "cc_batch_autotune": ([vp, i32, vp, f64, u32, vp, ctypes.POINTER(_BatchConfig)], i32),
+        "cc_mlp_forward": ([vp, vp, i64, vp, vp], i32),
+        "cc_mlp_train_step": ([vp, vp, vp, vp, vp, i64, i64, ctypes.c_float, vp, vp, vp], i32),
         "cc_set_eps_policy": ([i32, vp, ctypes.c_size_t, f64, f64], i32),
         "cc_last_error": ([], ctypes.c_char_p),
     }
@@ -281,6 +286,33 @@ def cc_batch_autotune(graph: Graph, order, algo: int = CC_ALGO_C4, eps: float = 
     _check(_lib.cc_batch_autotune(graph.handle, int(algo), po, float(eps), CC_INPUT_ON_DEVICE if odev else 0,
                                   _stream(stream, order), ctypes.byref(c)))
     return BatchConfig(c.block, c.wave_max_n, c.ms)
+
+
+def _dev(t, name):
+    if t is None:
+        return None
+    if not (_is_torch(t) and t.is_cuda and str(t.dtype) == "torch.float32" and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def cc_mlp_forward(params, x, y=None, stream=None):
+    """Network outputs for x[n, 6] (device tensors).  Returns y[n]."""
+    import torch
+    n = x.shape[0]
+    if y is None:
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(_lib.cc_mlp_forward(_dev(params, "params"), _dev(x, "x"), n, _dev(y, "y"), _stream(stream, x)))
+    return y
+
+
+def cc_mlp_train_step(params, adam_m, adam_v, x, target, step: int, lr: float, grad=None, loss=None, stream=None):
+    """Gradient of mean((y - target)^2) and, if lr > 0, one Adam step in place
+    (device tensors).  grad / loss, when given, receive the gradient and loss."""
+    n = x.shape[0]
+    _check(_lib.cc_mlp_train_step(_dev(params, "params"), _dev(adam_m, "adam_m"), _dev(adam_v, "adam_v"),
+                                  _dev(x, "x"), _dev(target, "target"), n, int(step), float(lr),
+                                  _dev(grad, "grad"), _dev(loss, "loss"), _stream(stream, x)))
 
 
 def cc_set_eps_policy(kind: int, params=None, eps_min: float = 1.0 / 16, eps_max: float = 16.0):

@@ -905,6 +905,44 @@ int32_t cc_batch_autotune(cc_graph *g, int32_t algo, const int32_t *order, doubl
   return autotune_batch(g, algo, order, eps, flags, (hipStream_t)stream, best);
 }
 
+int32_t cc_mlp_forward(const float *params, const float *x, int64_t n, float *y, void *stream) {
+  g_last_error.clear();
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(CC_ERR_INVALID_ARG, "n must lie in [0, 2^31)");
+  if (!params || (n > 0 && (!x || !y))) return fail(CC_ERR_INVALID_ARG, "params, x and y must not be NULL");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_mlp_forward(params, x, (int)n, y, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return CC_OK;
+}
+
+int32_t cc_mlp_train_step(float *params, float *adam_m, float *adam_v, const float *x, const float *target, int64_t n,
+                          int64_t step, float lr, float *grad, float *loss, void *stream) {
+  g_last_error.clear();
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(CC_ERR_INVALID_ARG, "n must lie in [0, 2^31)");
+  if (!params || (n > 0 && (!x || !target))) return fail(CC_ERR_INVALID_ARG, "params, x and target must not be NULL");
+  if (!(lr >= 0.f) || !std::isfinite(lr)) return fail(CC_ERR_INVALID_ARG, "lr must be finite and >= 0");
+  if (lr > 0.f && (!adam_m || !adam_v || step < 1))
+    return fail(CC_ERR_INVALID_ARG, "an Adam step needs adam_m, adam_v and step >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const int nblk = mlp_grad_blocks((int)n);
+  // partial gradient rows, one per workgroup; kept for later calls
+  static std::mutex mu;
+  static float *partial = nullptr;
+  static int cap = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (nblk > cap) {
+    if (partial) HIP_TRY(hipFree(partial));
+    partial = nullptr;
+    cap = 0;
+    HIP_TRY(dalloc(&partial, (size_t)1024 * 514));
+    cap = 1024;
+  }
+  HIP_TRY(launch_mlp_train_step(params, adam_m, adam_v, x, target, (int)n, (long long)step, lr, partial, nblk, grad,
+                                loss, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return CC_OK;
+}
+
 int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes, double eps_min, double eps_max) {
   g_last_error.clear();
   Policy p;

@@ -54,6 +54,12 @@ hipError_t launch_batched(const BatchLaunch &bl, hipStream_t s);
 size_t batched_lds_bytes(int block, int cap_big, int cap_wave);
 hipError_t batched_max_grid(int block, size_t lds, int *grid);
 
+// Learned-policy network: inference over a batch, one training step.
+int mlp_grad_blocks(int n);
+hipError_t launch_mlp_forward(const float *p, const float *x, int n, float *y, hipStream_t s);
+hipError_t launch_mlp_train_step(float *p, float *m, float *v, const float *x, const float *t, int n, long long step,
+                                 float lr, float *partial, int nblk, float *grad, float *loss, hipStream_t s);
+
 // Disagreement cost per graph: acc[2g] = pairs inside clusters, acc[2g+1] =
 // same-label adjacency entries (2 m_in); size is scratch [n].
 hipError_t launch_cost(const int64_t *off, const int32_t *col, const int64_t *wall, int64_t n,
