@@ -99,6 +99,9 @@ typedef struct cc_run_stats {
   int64_t trace_capacity;  /* in */
   int32_t *graph_rounds;   /* in: host int32[num_graphs] receiving each graph's rounds
                               (batches; rounds then holds their maximum), or NULL */
+  int64_t max_rounds;      /* in: 0 runs to completion; k > 0 stops after k rounds (single
+                              graphs only): a partial run whose still-unclustered vertices
+                              get label -1, used to measure one round from a replayed state */
 } cc_run_stats;
 
 /*

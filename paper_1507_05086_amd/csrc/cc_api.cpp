@@ -225,6 +225,9 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     return fail(CC_ERR_INVALID_ARG, "unknown flag for a run");
   if (stats && stats->trace_capacity > 0 && !stats->trace)
     return fail(CC_ERR_INVALID_ARG, "stats->trace is NULL but trace_capacity > 0");
+  if (stats && stats->max_rounds < 0) return fail(CC_ERR_INVALID_ARG, "stats->max_rounds must be >= 0");
+  if (stats && stats->max_rounds > 0 && g->num_graphs != 1)
+    return fail(CC_ERR_INVALID_ARG, "max_rounds applies to single graphs only");
   if (g->num_graphs != 1) return run_batch(g, algo, order, eps, labels, stats, flags, s);
   Policy pol;
   {
@@ -306,6 +309,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.mlp = ws.mlp;
   w.eps_min = (float)pol.eps_min;
   w.eps_max = (float)pol.eps_max;
+  w.max_rounds = stats ? stats->max_rounds : 0;
 
   // init: the permutation is checked before any kernel indexes with it
   HIP_TRY(hipMemsetAsync(ws.ctrl, 0, sizeof(Ctrl), s));

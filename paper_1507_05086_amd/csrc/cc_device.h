@@ -130,6 +130,7 @@ struct Ws {
   int64_t sched_len;
   const float *mlp;     // LEARNED: 6-64-1 weights (device)
   float eps_min, eps_max;
+  int64_t max_rounds;   // > 0: stop after this many rounds (partial run)
 };
 
 __host__ __device__ inline int level_of(int64_t x) {  // floor(log2(x)), x >= 1

@@ -869,7 +869,7 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
       c->d_max[j] = 0;
     }
     c->x_pack = 0;
-    if (c->n_rem <= 0 || c->error) c->done = 1;
+    if (c->n_rem <= 0 || c->error || (w.max_rounds > 0 && c->round >= w.max_rounds)) c->done = 1;
     n_rem = c->n_rem;
     delta = c->delta;
     round = c->round;
@@ -928,7 +928,9 @@ __global__ void __launch_bounds__(BS) k_finalize(Ws w, int32_t *labels) {
   const int64_t n = w.n;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
     const int32_t l = w.lab[v];
-    if (l < 0 || (int64_t)l >= n) {
+    if (l == INF && w.max_rounds > 0) {
+      labels[v] = -1;  // a partial run left v unclustered
+    } else if (l < 0 || (int64_t)l >= n) {
       set_error(w.ctrl, ERR_LABEL);
       labels[v] = -1;
     } else {

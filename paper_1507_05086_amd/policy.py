@@ -38,7 +38,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "policy_weights.json")
 CANDIDATES = [2.0 ** k / 16.0 for k in range(9)]
 EPS_MIN, EPS_MAX = 1.0 / 16.0, 16.0
-TAIL_EPS = 1000.0  # rounds after the measured one: finish fast, their records are not used
 
 
 def log(*a):
@@ -107,7 +106,8 @@ def lookahead(cc, gh, order, trace, i: int, repeats: int = 2):
         cc.cc_set_eps_policy(cc.CC_EPS_TRACE, np.concatenate([prefix, [b]]).astype(np.int64))
         t_best, done = None, 0
         for _ in range(repeats):
-            _, st = cc.cc_c4(gh, order, TAIL_EPS, labels=_scratch_labels(order), trace_capacity=i + 2)
+            _, st = cc.cc_c4(gh, order, 0.5, labels=_scratch_labels(order), trace_capacity=i + 2,
+                             max_rounds=i + 1)
             rec = st.trace[i]
             if int(rec["n_i"]) != n_i or int(rec["delta_i"]) != d_i or int(rec["b_i"]) != b:
                 raise RuntimeError(f"replay diverged at round {i}")
@@ -150,6 +150,7 @@ def collect(cc, gh, order, eps_bases, per_run: int, rng, weights=None):
         for i in pick_rounds(st.rounds, per_run, rng):
             Xs.append(X[i])
             ts.append(lookahead(cc, gh, order, tr, i))
+            log(f"  {kind} eps={e}: round {i}/{st.rounds} -> eps* {math.exp(ts[-1]):.3g}")
     return np.array(Xs), np.array(ts)
 
 

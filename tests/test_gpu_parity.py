@@ -211,3 +211,26 @@ def test_cost_arbitrary_labels(cc):
         assert int(cc.cc_cost(gh, lab)[0]) == oracle.cost(g.off, g.col, lab)
     with pytest.raises(cc.CCError):
         cc.cc_cost(gh, np.full(g.n, g.n, np.int32))
+
+
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+def test_partial_run_max_rounds(cc, algo):
+    """Stopping after k rounds gives the first k records of the full run; a
+    vertex clustered by then already has its final label, the rest get -1."""
+    g = graphgen.chung_lu(40_000, 2.1, 12.0, seed=51)
+    gh = upload(g)
+    order = graphgen.permutation(g.n, 51)
+    fn = cc.cc_c4 if algo == oracle.C4 else cc.cc_clusterwild
+    full, stf = fn(gh, order, 0.5)
+    for k in (1, 3, stf.rounds - 1, stf.rounds, stf.rounds + 5):
+        lab, st = fn(gh, order, 0.5, max_rounds=k)
+        kk = min(k, stf.rounds)
+        assert st.rounds == kk
+        for f in ("n_i", "delta_i", "b_i", "centers", "claimed"):
+            assert np.array_equal(st.trace[f], stf.trace[f][:kk])
+        done = lab >= 0
+        assert np.array_equal(lab[done], full[done])
+        left = int(stf.trace["n_i"][kk]) if kk < stf.rounds else 0
+        assert int((~done).sum()) == left
+    with pytest.raises(cc.CCError):
+        fn(gh, order, 0.5, max_rounds=-1)

@@ -142,3 +142,15 @@ def test_tiny_batches(n):
         assert L == 0.0 and not g.any()
     else:
         assert np.isfinite(g).all()
+
+
+def test_committed_policy_weights():
+    """The trained policy file loads, has 513 finite weights and a clamp range
+    inside the library's eps limits; its outputs on typical features are finite."""
+    from paper_1507_05086_amd import policy
+    w, lo, hi = policy.load()
+    assert w.shape == (mlp.NPARAM,) and np.isfinite(w).all()
+    assert 0 < lo <= hi <= 1000
+    for x in ([math.log(6.7e7), math.log(2e5), 0, 0, 0.5, 0], [math.log(1e5), math.log(30), 0.1, 0.3, 4.0, 120]):
+        e = mlp.policy_eps(w.astype(np.float64), np.array(x), lo, hi)
+        assert e is not None and lo <= e <= hi
