@@ -93,6 +93,15 @@ struct Ctrl {
   unsigned long long sum_elect, sum_claim, sum_rescan, sum_peel, sum_blocked, sum_atomics;
 };
 
+// A listed vertex's row: start of its adjacency in col, its degree and its
+// rank in pi.  Carried along the active and center lists so the passes over
+// those rows never look the offsets or the rank up again.
+struct RowInfo {
+  int64_t start;
+  int32_t deg;
+  int32_t rank;
+};
+
 struct Ws {
   // graph
   const int64_t *off;
@@ -108,6 +117,7 @@ struct Ws {
   // lists
   int32_t *alist, *clist, *nlist, *blist, *rlist, *xlist, *plist;
   int64_t *awork, *cwork, *nwork, *rwork, *xwork, *pwork;
+  RowInfo *ainfo, *cinfo;  // row info of alist / clist entries
   unsigned long long *racc;  // rescan accumulators (items covered << 32 | count), DITER * rcap
   int64_t rcap;         // capacity of one pass's rescan list
   int2 *cedge;
@@ -230,6 +240,26 @@ __device__ inline void wave_append(bool pred, int32_t v, int64_t weight, unsigne
   }
 }
 
+// wave_append for a list that carries row info (weight = max(deg, 1)).
+__device__ inline void wave_append_info(bool pred, int32_t v, RowInfo ri, unsigned long long *packc, int32_t *list,
+                                        int64_t *work, RowInfo *info) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0) return;
+  const int64_t w = pred ? (ri.deg > 0 ? ri.deg : 1) : 0;
+  const int64_t winc = wave_incl_scan(w);
+  const int64_t wtot = __shfl(winc, 63, 64);
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(packc, pk(wtot, __popcll(m)));
+  base = __shfl(base, leader, 64);
+  if (pred) {
+    const int64_t slot = pk_cnt(base) + __popcll(m & lanemask_lt());
+    list[slot] = v;
+    work[slot] = pk_work(base) + winc - w;
+    info[slot] = ri;
+  }
+}
+
 __device__ inline int64_t row_weight(const int64_t *off, int32_t v) {
   const int64_t d = off[v + 1] - off[v];
   return d > 0 ? d : 1;
@@ -271,6 +301,20 @@ struct StageBuf {
   int64_t sh[WAVES + 1];
 };
 
+// Staging buffer whose entries also carry row info.
+template <int CAP>
+struct StageBufI : StageBuf<CAP> {
+  RowInfo info[CAP];
+};
+
+template <int CAP>
+__device__ inline void stage_push_info(StageBufI<CAP> &b, int32_t v, RowInfo ri) {
+  const int p = atomicAdd(&b.cnt, 1);
+  b.id[p] = v;
+  b.wt[p] = ri.deg > 0 ? ri.deg : 1;
+  b.info[p] = ri;
+}
+
 template <int CAP>
 __device__ inline void stage_init(StageBuf<CAP> &b) {
   if (threadIdx.x == 0) b.cnt = 0;
@@ -287,7 +331,8 @@ __device__ inline void stage_push(StageBuf<CAP> &b, int32_t v, int32_t weight) {
 // Collective: every thread of the workgroup calls it.
 template <int CAP>
 __device__ inline void stage_flush(StageBuf<CAP> &b, unsigned long long *packc, int32_t *list, int64_t *work,
-                                   unsigned long long *zero_acc = nullptr) {
+                                   unsigned long long *zero_acc = nullptr, RowInfo *info = nullptr,
+                                   const RowInfo *staged = nullptr) {
   __syncthreads();
   const int cnt = b.cnt;
   if (cnt == 0) return;
@@ -307,6 +352,7 @@ __device__ inline void stage_flush(StageBuf<CAP> &b, unsigned long long *packc, 
   for (int i = threadIdx.x; i < cnt; i += BS) {
     list[slot0 + i] = b.id[i];
     if (zero_acc) zero_acc[slot0 + i] = 0;
+    if (info) info[slot0 + i] = staged[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) b.cnt = 0;

@@ -109,7 +109,7 @@ __device__ inline bool row_contains(const int64_t *off, const int32_t *col, int6
 }
 
 __global__ void __launch_bounds__(BS) k_check(CheckArgs a) {
-  lb_walk(nullptr, a.wall, a.n, a.wall[a.n], a.off, a.col, nullptr, [&](Items &it) {
+  lb_walk(nullptr, a.wall, a.n, a.wall[a.n], a.off, a.col, nullptr, nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
       if (!(it.edge >> k & 1)) continue;
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(BS) k_cost_sizes(CostArgs a) {
 __global__ void __launch_bounds__(BS) k_cost_same(CostArgs a) {
   int g_cur = -1;
   long long run = 0;
-  lb_walk(nullptr, a.wall, a.n, a.wall[a.n], a.off, a.col, a.labels, [&](Items &it) {
+  lb_walk(nullptr, a.wall, a.n, a.wall[a.n], a.off, a.col, a.labels, nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
       if (!(it.edge >> k & 1)) continue;

@@ -60,8 +60,9 @@ __global__ void __launch_bounds__(BS) k_invert(Ws w) {
 __global__ void __launch_bounds__(BS) k_init(Ws w, const unsigned *lvl_init_cnt) {
   const int64_t n = w.n;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
-    const int32_t r = w.rank[v];
-    if (r < 0 || (int64_t)r >= n || w.order[r] != (int32_t)v) set_error(w.ctrl, ERR_PERM);
+    // k_invert range-checked every entry of order; if every vertex also got
+    // a rank, the n entries hit n distinct vertices: order is a permutation
+    if (w.rank[v] < 0) set_error(w.ctrl, ERR_PERM);
     w.lab[v] = INF;
     w.state[v] = UNCL;
     w.flag[v] = 0;
@@ -265,7 +266,7 @@ __global__ void __launch_bounds__(BS) k_rescan(Ws w) {
     }
   };
   lb_walk(
-      w.rlist + IT * w.rcap, w.rwork + IT * w.rcap, cnt, pk_work(rp), w.off, w.col, nullptr,
+      w.rlist + IT * w.rcap, w.rwork + IT * w.rcap, cnt, pk_work(rp), w.off, w.col, nullptr, nullptr,
       [&](Items &it) {
 #pragma unroll
         for (int k = 0; k < IPT; k++)
@@ -346,7 +347,7 @@ __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
     else if (r >= HLDS) atomicAdd(&w.hist[r], 1);
   };
   lb_walk(
-      w.xlist, w.xwork, pk_cnt(xp), pk_work(xp), w.off, w.col, nullptr,
+      w.xlist, w.xwork, pk_cnt(xp), pk_work(xp), w.off, w.col, nullptr, nullptr,
       [&](Items &it) {
 #pragma unroll
         for (int k = 0; k < IPT; k++)
@@ -461,16 +462,19 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     int cnt = 0;
     unsigned act = 0;
     int32_t wt[SIPT];
+    int64_t rs[SIPT];
     long long r = excl + mine;
 #pragma unroll
     for (int k = 0; k < SIPT; k++) {
       wt[k] = 0;
+      rs[k] = 0;
       if (un & (1u << k)) {
         if (r < B) {
           act |= 1u << k;
           cnt++;
-          wt[k] = (int32_t)row_weight(w.off, vv[k]);
-          wsum += wt[k];
+          rs[k] = w.off[vv[k]];
+          wt[k] = (int32_t)(w.off[vv[k] + 1] - rs[k]);  // degree here; weight max(deg, 1) below
+          wsum += wt[k] > 0 ? wt[k] : 1;
           if (r == B - 1) {
             c->r_last = base + k;
             st_rel(&c->select_done, 1);
@@ -494,8 +498,9 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
           if (w.algo == ALGO_CW) w.lab[v] = (int32_t)(base + k);  // every active vertex is a center
           w.alist[slot] = v;
           w.awork[slot] = wpos;
+          w.ainfo[slot] = RowInfo{rs[k], wt[k], (int32_t)(base + k)};
           slot++;
-          wpos += wt[k];
+          wpos += wt[k] > 0 ? wt[k] : 1;
         }
       }
     }
@@ -510,7 +515,7 @@ __global__ void __launch_bounds__(BS) k_elect(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
   const unsigned long long ap = c->a_pack;
-  lb_walk(w.alist, w.awork, pk_cnt(ap), pk_work(ap), w.off, w.col, w.rank, [&](Items &it) {
+  lb_walk(w.alist, w.awork, pk_cnt(ap), pk_work(ap), w.off, w.col, nullptr, w.ainfo, [&](Items &it) {
     uint8_t su[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; k++) su[k] = (it.edge >> k & 1) ? w.state[it.u[k]] : (uint8_t)UNCL;
@@ -539,7 +544,7 @@ __global__ void __launch_bounds__(BS) k_elect(Ws w) {
 __global__ void __launch_bounds__(BS) k_classify(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
-  __shared__ StageBuf<2 * BS> sb;
+  __shared__ StageBufI<2 * BS> sb;
   stage_init(sb);
   const int64_t na = pk_cnt(c->a_pack);
   const int64_t per = ((na + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
@@ -552,9 +557,10 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
       a = w.alist[i];
       blocked = w.flag[a] != 0;
       if (!blocked) {
+        const RowInfo ri = w.ainfo[i];
         w.state[a] = CENTER;
-        w.lab[a] = w.rank[a];
-        stage_push(sb, a, (int32_t)row_weight(w.off, a));
+        w.lab[a] = ri.rank;
+        stage_push_info(sb, a, ri);
       }
     }
     const unsigned long long m = __ballot(blocked);  // blocked vertices are rare
@@ -566,9 +572,9 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
       if (blocked) w.blist[base + __popcll(m & lanemask_lt())] = a;
     }
     __syncthreads();
-    if (sb.cnt > BS) stage_flush(sb, &c->c_pack, w.clist, w.cwork);
+    if (sb.cnt > BS) stage_flush(sb, &c->c_pack, w.clist, w.cwork, nullptr, w.cinfo, sb.info);
   }
-  stage_flush(sb, &c->c_pack, w.clist, w.cwork);
+  stage_flush(sb, &c->c_pack, w.clist, w.cwork, nullptr, w.cinfo, sb.info);
 }
 
 // One workgroup: a blocked vertex is a non-center as soon as an earlier
@@ -611,12 +617,14 @@ __global__ void __launch_bounds__(BS) k_resolve(Ws w) {
             else waiting = true;
           }
         }
+        RowInfo ri{0, 0, 0};
         if (promote) {
+          ri = RowInfo{w.off[a], (int32_t)(w.off[a + 1] - w.off[a]), w.rank[a]};
           w.state[a] = CENTER;
-          w.lab[a] = w.rank[a];
+          w.lab[a] = ri.rank;
         }
         if (waiting) s_any = 1;
-        wave_append(promote, a, promote ? row_weight(w.off, a) : 0, &c->c_pack, w.clist, w.cwork);
+        wave_append_info(promote, a, ri, &c->c_pack, w.clist, w.cwork, w.cinfo);
       }
       __syncthreads();
       if (!s_any) break;
@@ -650,11 +658,13 @@ __global__ void __launch_bounds__(BS) k_resolve(Ws w) {
             else s_any = 1;
           }
         }
+        RowInfo ri{0, 0, 0};
         if (promote) {
+          ri = RowInfo{w.off[a], (int32_t)(w.off[a + 1] - w.off[a]), w.rank[a]};
           w.state[a] = CENTER;
-          w.lab[a] = w.rank[a];
+          w.lab[a] = ri.rank;
         }
-        wave_append(promote, a, promote ? row_weight(w.off, a) : 0, &c->c_pack, w.clist, w.cwork);
+        wave_append_info(promote, a, ri, &c->c_pack, w.clist, w.cwork, w.cinfo);
       }
       __syncthreads();
       if (!s_any) break;
@@ -674,12 +684,13 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   const unsigned long long lp = c4 ? c->c_pack : c->a_pack;
   const int32_t *list = c4 ? w.clist : w.alist;
   const int64_t *work = c4 ? w.cwork : w.awork;
+  const RowInfo *info = c4 ? w.cinfo : w.ainfo;
   __shared__ unsigned s_atom;
   __shared__ StageBuf<CLAIM_CAP> sb;
   if (threadIdx.x == 0) s_atom = 0;
   stage_init(sb);
   lb_walk(
-      list, work, pk_cnt(lp), pk_work(lp), w.off, w.col, w.rank,
+      list, work, pk_cnt(lp), pk_work(lp), w.off, w.col, nullptr, info,
       [&](Items &it) {
         // every center is clustered this round
 #pragma unroll
@@ -775,7 +786,7 @@ __global__ void __launch_bounds__(BS) k_peel(Ws w) {
   if (threadIdx.x == 0) s_atom = 0;
   __syncthreads();
   const unsigned long long pp = c->p_pack;
-  lb_walk(w.plist, w.pwork, pk_cnt(pp), pk_work(pp), w.off, w.col, nullptr, [&](Items &it) {
+  lb_walk(w.plist, w.pwork, pk_cnt(pp), pk_work(pp), w.off, w.col, nullptr, nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++)
       if (it.vert >> k & 1) hist_add(s_hist, w.hist, w.ub[it.v[k]], -1);  // the vertex leaves
@@ -934,7 +945,7 @@ __global__ void __launch_bounds__(BS) k_finalize(Ws w, int32_t *labels) {
       set_error(w.ctrl, ERR_LABEL);
       labels[v] = -1;
     } else {
-      labels[v] = w.order[l];
+      labels[v] = l == w.rank[v] ? (int32_t)v : w.order[l];  // a center is its own label
     }
   }
 }

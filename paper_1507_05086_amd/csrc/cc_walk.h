@@ -48,6 +48,7 @@ struct NoPost {
 // Calls f(Items&) once per tile in every thread of the workgroup (uniformly,
 // so f may use wave-wide operations).  `vals` (may be null) is gathered per
 // row into Items::val.  A null `list` means the rows 0..cnt-1 themselves.
+// With `info` (per list entry), rows come from it and Items::val is the rank.
 // After f, ep(j, slot, v, deg, covered) runs once for every row j the tile
 // touched (slot = list index, covered = items of that row in this tile), so
 // per-row partial results kept in LDS by f can be combined across tiles; then
@@ -55,7 +56,8 @@ struct NoPost {
 template <class F, class E = NoEpilogue, class P = NoPost>
 __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restrict__ work, int64_t cnt,
                         int64_t total, const int64_t *__restrict__ off, const int32_t *__restrict__ col,
-                        const int32_t *__restrict__ vals, F &&f, E &&ep = E(), P &&post = P()) {
+                        const int32_t *__restrict__ vals, const RowInfo *__restrict__ info, F &&f, E &&ep = E(),
+                        P &&post = P()) {
   __shared__ int64_t lw[TW + 1];
   __shared__ int32_t lv[TW];
   __shared__ int64_t loff[TW];
@@ -92,11 +94,18 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
     const int nent = s_nent;
     for (int j = threadIdx.x; j < nent; j += BS) {
       const int32_t v = list ? list[ent0 + j] : (int32_t)(ent0 + j);
-      const int64_t o = off[v];
       lv[j] = v;
-      loff[j] = o;
-      ldeg[j] = (int32_t)(off[v + 1] - o);
-      lval[j] = vals ? vals[v] : 0;
+      if (info) {  // row info carried by the list: no offset or rank lookups
+        const RowInfo ri = info[ent0 + j];
+        loff[j] = ri.start;
+        ldeg[j] = ri.deg;
+        lval[j] = ri.rank;
+      } else {
+        const int64_t o = off[v];
+        loff[j] = o;
+        ldeg[j] = (int32_t)(off[v + 1] - o);
+        lval[j] = vals ? vals[v] : 0;
+      }
     }
     __syncthreads();
     Items it;
