@@ -72,7 +72,7 @@ struct Workspace {
   Ctrl *ctrl = nullptr;
   RoundRec *trace = nullptr;
   int64_t trace_cap = 0;
-  int32_t *order_buf = nullptr, *label_buf = nullptr;
+  int32_t *order_buf = nullptr, *label_buf = nullptr, *iorder = nullptr;
   int64_t *sched = nullptr;
   int64_t sched_cap = 0;
   float *mlp = nullptr;
@@ -111,6 +111,9 @@ struct cc_graph {
   int64_t *vtx_ptr = nullptr;  // device, batches only
   int32_t *gid = nullptr;      // device, batches only
   int64_t *wall = nullptr;     // device [n+1]
+  // single graphs: internal renumbering (hubs first) and the renumbered CSR
+  int32_t *perm = nullptr, *iperm = nullptr, *rcol = nullptr;
+  int64_t *roff = nullptr;
   int64_t max_deg = 0;
   int64_t n_hi = 0;            // vertices with degree >= DSW
   int32_t *lvl_init = nullptr; // device: initial bound buckets
@@ -129,6 +132,7 @@ void free_ws(Workspace &w) {
   void *ptrs[] = {w.rank, w.lab, w.ub, w.unc, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
                   w.awork, w.cwork, w.nwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist, w.plist, w.pwork,
                   w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf, w.label_buf, w.sched, w.mlp, w.ainfo, w.cinfo,
+                  w.iorder,
                   w.cost_size, w.cost_acc, w.dev_err};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -152,6 +156,11 @@ void free_graph(cc_graph *g) {
   if (g->vtx_ptr) (void)hipFree(g->vtx_ptr);
   if (g->gid) (void)hipFree(g->gid);
   if (g->wall) (void)hipFree(g->wall);
+  {
+    void *ptrs[] = {g->perm, g->iperm, g->rcol, g->roff};
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+  }
   if (g->lvl_init) (void)hipFree(g->lvl_init);
   if (g->lvl_off) (void)hipFree(g->lvl_off);
   if (g->lvl_cnt0) (void)hipFree(g->lvl_cnt0);
@@ -198,6 +207,7 @@ int32_t ensure_ws(cc_graph *g) {
   HIP_TRY(dalloc(&w.trace, (size_t)w.trace_cap));
   HIP_TRY(dalloc(&w.order_buf, n));
   HIP_TRY(dalloc(&w.label_buf, n));
+  HIP_TRY(dalloc(&w.iorder, n));
   HIP_TRY(dalloc(&w.mlp, CC_MLP_PARAMS));
   HIP_TRY(dalloc(&w.cost_size, n));
   HIP_TRY(dalloc(&w.cost_acc, 2 * (size_t)g->num_graphs));
@@ -267,10 +277,14 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     HIP_TRY(hipMemcpyAsync(ws.mlp, pol.mlp.data(), sizeof(float) * CC_MLP_PARAMS, hipMemcpyHostToDevice, s));
 
   Ws w{};
-  w.off = g->off;
-  w.col = g->col;
+  w.off = g->roff;
+  w.col = g->rcol;
   w.n = n;
-  w.order = d_order;
+  w.order = ws.iorder;
+  w.iorder = ws.iorder;
+  w.order_in = d_order;
+  w.perm = g->perm;
+  w.iperm = g->iperm;
   w.max_deg = g->max_deg;
   w.rank = ws.rank;
   w.lab = ws.lab;
@@ -784,15 +798,36 @@ int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_
   (void)hipFree(blocksum);
   (void)hipFree(derr);
   G_TRY(e);
+  if (herr == none && n_total > 0 && num_graphs == 1) {
+    G_TRY(dalloc(&g->perm, (size_t)n_total));
+    G_TRY(dalloc(&g->iperm, (size_t)n_total));
+    G_TRY(dalloc(&g->roff, (size_t)n_total + 1));
+    G_TRY(dalloc(&g->rcol, (size_t)nnz));
+    unsigned *cnt = nullptr;
+    int64_t *binoff = nullptr, *rdeg = nullptr, *bsum = nullptr;
+    hipError_t re = dalloc(&cnt, 2 * (NLVL + 1));
+    if (re == hipSuccess) re = dalloc(&binoff, NLVL + 1);
+    if (re == hipSuccess) re = dalloc(&rdeg, (size_t)n_total);
+    if (re == hipSuccess) re = dalloc(&bsum, (size_t)(n_total / (4 * BS) + 4));
+    if (re == hipSuccess)
+      re = launch_relabel(g->off, g->col, g->wall, n_total, cnt, binoff, g->perm, g->iperm, rdeg, g->roff, bsum,
+                          g->rcol, s);
+    if (re == hipSuccess) re = hipStreamSynchronize(s);
+    void *tmp[] = {cnt, binoff, rdeg, bsum};
+    for (void *p : tmp)
+      if (p) (void)hipFree(p);
+    G_TRY(re);
+  }
   if (herr == none && n_total > 0) {
-    // bound buckets: capacity of level k = vertices of degree >= 2^k
+    // bound buckets: capacity of level k = vertices of degree >= 2^k (internal ids)
+    const int64_t *xoff = g->roff ? g->roff : g->off;
     unsigned *dcnt = nullptr;
     int *dmax = nullptr;
     G_TRY(dalloc(&dcnt, NLVL));
     G_TRY(dalloc(&dmax, 1));
     G_TRY(hipMemsetAsync(dcnt, 0, sizeof(unsigned) * NLVL, s));
     G_TRY(hipMemsetAsync(dmax, 0, sizeof(int), s));
-    G_TRY(launch_level_count(g->off, n_total, dcnt, dmax, s));
+    G_TRY(launch_level_count(xoff, n_total, dcnt, dmax, s));
     unsigned hcnt[NLVL];
     int hmax = 0;
     G_TRY(hipMemcpyAsync(hcnt, dcnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
@@ -818,7 +853,7 @@ int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_
     G_TRY(hipMemcpyAsync(g->lvl_off, hoff, sizeof(hoff), hipMemcpyHostToDevice, s));
     G_TRY(hipMemcpyAsync(g->lvl_cnt0, hcnt, sizeof(hcnt), hipMemcpyHostToDevice, s));
     G_TRY(hipMemsetAsync(dcnt, 0, sizeof(unsigned) * NLVL, s));
-    G_TRY(launch_level_fill(g->off, n_total, g->lvl_off, dcnt, g->lvl_init, s));
+    G_TRY(launch_level_fill(xoff, n_total, g->lvl_off, dcnt, g->lvl_init, s));
     G_TRY(hipStreamSynchronize(s));
     (void)hipFree(dcnt);
     (void)hipFree(dmax);

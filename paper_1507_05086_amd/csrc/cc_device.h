@@ -109,7 +109,11 @@ struct Ws {
   int64_t n;
   int64_t max_deg;
   // run input
-  const int32_t *order;
+  const int32_t *order;     // pi in internal ids (written by k_invert)
+  int32_t *iorder;          // the same buffer, writable
+  const int32_t *order_in;  // the caller's pi (input ids)
+  const int32_t *perm;      // input id -> internal id
+  const int32_t *iperm;     // internal id -> input id
   // per-vertex arrays
   int32_t *rank, *lab, *ub;
   uint32_t *unc;

@@ -218,6 +218,124 @@ hipError_t launch_level_fill(const int64_t *off, int64_t n, const int64_t *lvl_o
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------- renumbering --
+// Internal vertex ids group the vertices by degree level floor(log2 deg),
+// highest level first and isolated vertices last.  A neighbour scan touches
+// a vertex about as often as its degree, so the per-vertex state it reads
+// most (that of the hubs) sits in a few contiguous lines that stay cached.
+// Within a level the order is whatever the atomics give: no result depends
+// on internal ids (labels and every record are mapped back or id-free).
+constexpr int RBINS = NLVL + 1;
+__device__ inline int relabel_bin(int64_t d) { return d > 0 ? NLVL - 1 - level_of(d) : NLVL; }
+
+__global__ void __launch_bounds__(BS) k_relabel_count(const int64_t *off, int64_t n, unsigned *count) {
+  __shared__ unsigned s_cnt[RBINS];
+  if (threadIdx.x < RBINS) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS)
+    atomicAdd(&s_cnt[relabel_bin(off[v + 1] - off[v])], 1u);
+  __syncthreads();
+  if (threadIdx.x < RBINS && s_cnt[threadIdx.x]) atomicAdd(&count[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+// Each workgroup takes a contiguous chunk, reserves its range in every bin
+// with one atomic, then places its vertices.
+__global__ void __launch_bounds__(BS) k_relabel_assign(const int64_t *off, int64_t n, const int64_t *bin_off,
+                                                       unsigned *cursor, int32_t *perm, int32_t *iperm) {
+  __shared__ unsigned s_cnt[RBINS], s_base[RBINS];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t v0 = (int64_t)blockIdx.x * per, v1 = v0 + per < n ? v0 + per : n;
+  if (threadIdx.x < RBINS) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += BS) atomicAdd(&s_cnt[relabel_bin(off[v + 1] - off[v])], 1u);
+  __syncthreads();
+  if (threadIdx.x < RBINS) {
+    s_base[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], s_cnt[threadIdx.x]) : 0u;
+    s_cnt[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += BS) {
+    const int b = relabel_bin(off[v + 1] - off[v]);
+    const int64_t p = bin_off[b] + s_base[b] + atomicAdd(&s_cnt[b], 1u);
+    perm[v] = (int32_t)p;
+    iperm[p] = (int32_t)v;
+  }
+}
+
+// rdeg[i] = degree of internal vertex i (its original row's length)
+__global__ void __launch_bounds__(BS) k_relabel_degrees(const int64_t *off, int64_t n, const int32_t *iperm,
+                                                        int64_t *rdeg) {
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const int32_t v = iperm[i];
+    rdeg[i] = off[v + 1] - off[v];
+  }
+}
+
+// Exclusive scan of rdeg into roff (block partial sums, then their scan, then add).
+__global__ void __launch_bounds__(BS) k_plain_scan_local(const int64_t *x_in, int64_t n, int64_t *out,
+                                                         int64_t *blocksum) {
+  __shared__ int64_t sh[WAVES + 1];
+  const int64_t base = ((int64_t)blockIdx.x * BS + threadIdx.x) * SCAN_T;
+  int64_t x[SCAN_T], s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_T; k++) {
+    x[k] = base + k < n ? x_in[base + k] : 0;
+    s += x[k];
+  }
+  int64_t tot;
+  int64_t pre = wg_excl_scan(s, &tot, sh);
+#pragma unroll
+  for (int k = 0; k < SCAN_T; k++) {
+    if (base + k < n) out[base + k] = pre;
+    pre += x[k];
+  }
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
+}
+
+// rcol[roff[perm[v]] + j] = perm[col[off[v] + j]], edge-balanced over the input rows.
+__global__ void __launch_bounds__(BS) k_relabel_cols(const int64_t *off, const int32_t *col, const int64_t *wall,
+                                                     int64_t n, const int32_t *perm, const int64_t *roff,
+                                                     int32_t *rcol) {
+  lb_walk(nullptr, wall, n, wall[n], off, col, perm, nullptr, [&](Items &it) {
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+      if (!(it.edge >> k & 1)) continue;
+      const int64_t local = it.pos[k] - off[it.v[k]];
+      rcol[roff[it.val[k]] + local] = perm[it.u[k]];
+    }
+  });
+}
+
+hipError_t launch_relabel(const int64_t *off, const int32_t *col, const int64_t *wall, int64_t n, unsigned *count,
+                          int64_t *bin_off_dev, int32_t *perm, int32_t *iperm, int64_t *rdeg, int64_t *roff,
+                          int64_t *blocksum, int32_t *rcol, hipStream_t s) {
+  if (n == 0) return hipMemsetAsync(roff, 0, sizeof(int64_t), s);
+  const unsigned g = (unsigned)((n + BS - 1) / BS < 4096 ? (n + BS - 1) / BS : 4096);
+  hipError_t e = hipMemsetAsync(count, 0, sizeof(unsigned) * 2 * RBINS, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_relabel_count, dim3(g), dim3(BS), 0, s, off, n, count);
+  unsigned hc[RBINS];
+  e = hipMemcpyAsync(hc, count, sizeof(hc), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  int64_t hb[RBINS], acc = 0;
+  for (int b = 0; b < RBINS; b++) {
+    hb[b] = acc;
+    acc += hc[b];
+  }
+  e = hipMemcpyAsync(bin_off_dev, hb, sizeof(hb), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_relabel_assign, dim3(g), dim3(BS), 0, s, off, n, bin_off_dev, count + RBINS, perm, iperm);
+  hipLaunchKernelGGL(k_relabel_degrees, dim3(g), dim3(BS), 0, s, off, n, iperm, rdeg);
+  const int64_t per = (int64_t)BS * SCAN_T;
+  const int64_t nb = (n + per - 1) / per;
+  hipLaunchKernelGGL(k_plain_scan_local, dim3((unsigned)nb), dim3(BS), 0, s, rdeg, n, roff, blocksum);
+  hipLaunchKernelGGL(k_wscan_blocks, dim3(1), dim3(BS), 0, s, blocksum, nb, blocksum + nb);
+  hipLaunchKernelGGL(k_wscan_add, dim3((unsigned)nb), dim3(BS), 0, s, roff, n, blocksum, blocksum + nb);
+  hipLaunchKernelGGL(k_relabel_cols, dim3(4096), dim3(BS), 0, s, off, col, wall, n, perm, roff, rcol);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ cost --
 
 struct CostArgs {

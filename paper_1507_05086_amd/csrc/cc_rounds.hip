@@ -46,14 +46,20 @@ __device__ inline bool row_combine(unsigned long long *acc, int64_t slot, int cn
 
 // ------------------------------------------------------------------ init --
 
-// rank = order^-1 by a plain scatter; k_init checks order[rank[v]] == v for
-// every v, which fails for a missing (hence also for a repeated) vertex.
+// pi moves to internal ids and rank = pi^-1 by a plain scatter; k_init then
+// finds a missing (hence also a repeated) vertex as one left without a rank.
 __global__ void __launch_bounds__(BS) k_invert(Ws w) {
   const int64_t n = w.n;
   for (int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x; k < n; k += (int64_t)gridDim.x * BS) {
-    const int32_t v = w.order[k];
-    if (v < 0 || (int64_t)v >= n) set_error(w.ctrl, ERR_PERM);
-    else w.rank[v] = (int32_t)k;
+    const int32_t v = w.order_in[k];
+    if (v < 0 || (int64_t)v >= n) {
+      set_error(w.ctrl, ERR_PERM);
+      w.iorder[k] = 0;
+    } else {
+      const int32_t vi = w.perm[v];
+      w.iorder[k] = vi;
+      w.rank[vi] = (int32_t)k;
+    }
   }
 }
 
@@ -938,14 +944,16 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
 __global__ void __launch_bounds__(BS) k_finalize(Ws w, int32_t *labels) {
   const int64_t n = w.n;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
+    // labels are indexed and valued in input ids
     const int32_t l = w.lab[v];
+    const int32_t vin = w.iperm[v];
     if (l == INF && w.max_rounds > 0) {
-      labels[v] = -1;  // a partial run left v unclustered
+      labels[vin] = -1;  // a partial run left v unclustered
     } else if (l < 0 || (int64_t)l >= n) {
       set_error(w.ctrl, ERR_LABEL);
-      labels[v] = -1;
+      labels[vin] = -1;
     } else {
-      labels[v] = l == w.rank[v] ? (int32_t)v : w.order[l];  // a center is its own label
+      labels[vin] = l == w.rank[v] ? vin : w.order_in[l];  // a center is its own label
     }
   }
 }

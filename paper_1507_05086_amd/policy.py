@@ -6,12 +6,16 @@ six features of the run so far (see ``cc_set_eps_policy`` in include/cc.h).
 C4's labels do not depend on the schedule (Section 3: C4 is serializable), so
 the policy can only change the number of rounds and the time.
 
-Labels (one-round look-ahead).  A state is the loop just before round i of a
-recorded run.  It is rebuilt exactly by replaying the recorded batch sizes
-B_0..B_{i-1} through the TRACE policy; round i then runs with
-B = ceil(eps_k n_i / Delta_i) for each candidate eps_k in {2^k / 16 : k =
-0..8}, and the candidate with the most vertices clustered per microsecond of
-that round is the target eps*.  Regression target: ln eps*.
+Labels (rollout from a replayed state).  A state is the loop just before
+round i of a recorded run.  It is rebuilt exactly by replaying the recorded
+batch sizes B_0..B_{i-1} through the TRACE policy; the rest of the run then
+uses the fixed rule with each candidate eps_k in {2^k / 16 : k = 0..8}, and
+the candidate whose whole run is fastest is the target eps* (the replayed
+prefix is the same for every candidate, so comparing whole runs compares the
+remainders).  A one-round look-ahead (most vertices clustered per microsecond
+of round i) is also available; it is myopic: it favours very large rounds,
+whose conflict resolution grows faster than their work.  Regression target:
+ln eps*.
 
 States come from runs of the fixed rule at several eps and, in later passes,
 from runs of the policy being trained (so it also learns the states it visits
@@ -121,6 +125,23 @@ def lookahead(cc, gh, order, trace, i: int, repeats: int = 2):
     return float(np.mean(np.log(best)))
 
 
+def rollout(cc, gh, order, trace, i: int, repeats: int = 2):
+    """ln eps* of the state before round i of `trace`: the candidate whose
+    remaining run (fixed rule from round i on) is fastest."""
+    prefix = np.asarray(trace["b_i"][:i], np.int64)
+    best, best_t = None, float("inf")
+    for e in CANDIDATES:
+        cc.cc_set_eps_policy(cc.CC_EPS_TRACE, prefix)
+        t = float("inf")
+        for _ in range(repeats):
+            _, st = cc.cc_c4(gh, order, e, labels=_scratch_labels(order), trace_capacity=0)
+            t = min(t, st.loop_ms)
+        if t < best_t:
+            best_t, best = t, e
+    cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+    return math.log(best)
+
+
 _lab_cache = {}
 
 
@@ -133,7 +154,7 @@ def _scratch_labels(order):
     return _lab_cache[key]
 
 
-def collect(cc, gh, order, eps_bases, per_run: int, rng, weights=None):
+def collect(cc, gh, order, eps_bases, per_run: int, rng, weights=None, label="rollout"):
     """(X, t) samples from runs of the fixed rule at each eps in eps_bases
     and, if `weights` is given, of that policy."""
     Xs, ts = [], []
@@ -149,7 +170,7 @@ def collect(cc, gh, order, eps_bases, per_run: int, rng, weights=None):
         X = trace_features(tr, e)
         for i in pick_rounds(st.rounds, per_run, rng):
             Xs.append(X[i])
-            ts.append(lookahead(cc, gh, order, tr, i))
+            ts.append(rollout(cc, gh, order, tr, i) if label == "rollout" else lookahead(cc, gh, order, tr, i))
             log(f"  {kind} eps={e}: round {i}/{st.rounds} -> eps* {math.exp(ts[-1]):.3g}")
     return np.array(Xs), np.array(ts)
 
@@ -213,6 +234,7 @@ def main():
     tr.add_argument("--lr", type=float, default=3e-3)
     tr.add_argument("--seed", type=int, default=7)
     tr.add_argument("--out", default=WEIGHTS)
+    tr.add_argument("--label", choices=("rollout", "lookahead"), default="rollout")
     args = ap.parse_args()
 
     import torch
@@ -237,7 +259,7 @@ def main():
     for ps in range(args.passes):
         for name, gh, order, _ in graphs:
             t0 = time.perf_counter()
-            X, t = collect(cc, gh, order, bases if ps == 0 else [], args.per_run, rng, weights)
+            X, t = collect(cc, gh, order, bases if ps == 0 else [], args.per_run, rng, weights, args.label)
             X_all = np.concatenate([X_all, X])
             t_all = np.concatenate([t_all, t])
             log(f"pass {ps} {name}: {len(t)} labelled states in {time.perf_counter() - t0:.1f} s "
@@ -245,7 +267,8 @@ def main():
         weights, loss = train_mlp(cc, X_all, t_all, args.steps, args.lr, args.seed + ps)
         log(f"pass {ps}: trained on {len(t_all)} states, final mse {loss:.4f}")
     save(weights, {"trained_on": [n for n, *_ in graphs], "samples": int(len(t_all)), "mse": loss,
-                   "label": "one-round look-ahead, vertices clustered per microsecond",
+                   "label": "rollout: fastest fixed eps for the rest of the run" if args.label == "rollout"
+                   else "one-round look-ahead, vertices clustered per microsecond",
                    "candidates": CANDIDATES}, path=args.out)
     log(f"wrote {args.out}")
 

@@ -1,0 +1,81 @@
+"""Parity at the full sizes of the two large single-graph workloads, in the
+launch configuration the benchmark times (graph, order and labels resident on
+the device, fixed rule).
+
+- Chung-Lu power law, n = 2,000,000, gamma = 2.1, mean degree 40 (about 40 M
+  positive edges): labels and the whole round trace against the oracle for
+  C4 and ClusterWild! at eps 0.1, 0.5 and 0.9.
+- R-MAT scale 26 (about 1.05 G positive edges), eps = 0.5: C4 labels by the
+  any-size KwikCluster checker (centers independent and maximal in pi order,
+  every vertex on its lowest-rank adjacent center) and ClusterWild! labels and
+  trace against the oracle's round loop.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_common import assert_labels_equal, assert_trace_equal, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cc():
+    torch_cuda()
+    import paper_1507_05086_amd as cc
+    cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+    return cc
+
+
+def resident(cc, g, seed):
+    torch = torch_cuda()
+    off = torch.from_numpy(np.ascontiguousarray(g.off)).cuda()
+    col = torch.from_numpy(np.ascontiguousarray(g.col)).cuda()
+    gh = cc.cc_graph_from_csr(off, col, borrow=True)
+    order = graphgen.permutation(g.n, seed)
+    return gh, (off, col), order, torch.from_numpy(order).cuda()
+
+
+def run(cc, algo, gh, dorder, eps):
+    torch = torch_cuda()
+    fn = cc.cc_c4 if algo == oracle.C4 else cc.cc_clusterwild
+    lab = torch.empty(dorder.numel(), dtype=torch.int32, device="cuda")
+    _, st = fn(gh, dorder, eps, labels=lab, trace_capacity=1 << 16)
+    torch.cuda.synchronize()
+    return lab.cpu().numpy(), st
+
+
+@pytest.fixture(scope="module")
+def chunglu(cc):
+    g = graphgen.workload("chunglu2m")
+    return (g, *resident(cc, g, 21))
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("eps", [0.1, 0.5, 0.9])
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+def test_chunglu_2m(cc, chunglu, algo, eps):
+    g, gh, _keep, order, dorder = chunglu
+    lab, st = run(cc, algo, gh, dorder, eps)
+    ref = oracle.bsp(algo, g.off, g.col, order, eps)
+    assert_labels_equal(lab, ref.labels, f"Chung-Lu 2M eps={eps}")
+    assert st.rounds == ref.rounds
+    assert_trace_equal(st.trace, ref.trace, ref.rounds)
+    if algo == oracle.C4:
+        assert oracle.check_kc(g.off, g.col, order, lab) == (0, -1)
+
+
+@pytest.mark.timeout(900)
+def test_rmat26(cc):
+    g = graphgen.workload("rmat26")
+    gh, _keep, order, dorder = resident(cc, g, 31)
+    lab, st = run(cc, oracle.C4, gh, dorder, 0.5)
+    bad, first = oracle.check_kc(g.off, g.col, order, lab)
+    assert bad == 0, f"C4 on R-MAT 26: {bad} vertices break KwikCluster, first {first}"
+    assert int(cc.cc_cost(gh, lab)[0]) == oracle.cost(g.off, g.col, lab)
+    lab, st = run(cc, oracle.CW, gh, dorder, 0.5)
+    ref = oracle.bsp(oracle.CW, g.off, g.col, order, 0.5)
+    assert_labels_equal(lab, ref.labels, "ClusterWild! on R-MAT 26")
+    assert st.rounds == ref.rounds
+    assert_trace_equal(st.trace, ref.trace, ref.rounds)
