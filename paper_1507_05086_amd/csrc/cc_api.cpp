@@ -49,6 +49,15 @@ struct Policy {
 Policy g_policy;
 std::mutex g_policy_mu;
 
+// A captured group of k rounds (kernels only), keyed by the bytes of the
+// run's kernel arguments and the phase it was captured for.
+struct RoundGraph {
+  unsigned char key[sizeof(Ws)];
+  int exact = -1;
+  int64_t k = 0;
+  hipGraphExec_t exec = nullptr;
+};
+
 // Device workspace of a run (allocated on the first run of a graph).
 struct Workspace {
   bool ready = false;
@@ -80,6 +89,8 @@ struct Workspace {
   int32_t *cost_size = nullptr;
   long long *cost_acc = nullptr;
   int *dev_err = nullptr;
+  hipStream_t cap = nullptr;  // private stream the round groups are captured on
+  std::vector<RoundGraph> graphs;
 };
 
 // Device buffers and launch shape of a batch.
@@ -137,6 +148,9 @@ void free_ws(Workspace &w) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (w.host_flags) (void)hipHostFree(w.host_flags);
+  for (RoundGraph &g : w.graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (w.cap) (void)hipStreamDestroy(w.cap);
   w = Workspace();
 }
 
@@ -228,6 +242,40 @@ int32_t wall_clock_khz(int *khz) {
 int32_t run_batch(cc_graph *g, int algo, const int32_t *order, double eps, int32_t *labels, cc_run_stats *stats,
                   uint32_t flags, hipStream_t s);
 
+// Queues k rounds on s as one graph launch: the round's kernels are captured
+// once per (arguments, phase, k) and replayed; the host then issues one call
+// per group instead of ~16 launches per round.
+int32_t launch_rounds(Workspace &ws, const Ws &w, const LaunchShape &ls, int64_t k, hipStream_t s) {
+  for (RoundGraph &g : ws.graphs)
+    if (g.k == k && g.exact == ls.exact_seen && std::memcmp(g.key, &w, sizeof(Ws)) == 0) {
+      HIP_TRY(hipGraphLaunch(g.exec, s));
+      return CC_OK;
+    }
+  if (!ws.cap) HIP_TRY(hipStreamCreateWithFlags(&ws.cap, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(ws.cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int64_t r = 0; r < k && e == hipSuccess; r++) e = launch_round(w, ws.cap, ls);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(ws.cap, &graph);
+  if (e == hipSuccess) e = e2;
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  HIP_TRY(e);
+  if (ws.graphs.size() >= 24) {  // keep the cache small: drop the oldest
+    (void)hipGraphExecDestroy(ws.graphs.front().exec);
+    ws.graphs.erase(ws.graphs.begin());
+  }
+  RoundGraph rg;
+  std::memcpy(rg.key, &w, sizeof(Ws));
+  rg.exact = ls.exact_seen;
+  rg.k = k;
+  rg.exec = exec;
+  ws.graphs.push_back(rg);
+  HIP_TRY(hipGraphLaunch(exec, s));
+  return CC_OK;
+}
+
 int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_t *labels,
                  cc_run_stats *stats, uint32_t flags, hipStream_t s) {
   if (!g) return fail(CC_ERR_INVALID_ARG, "graph handle is NULL");
@@ -276,7 +324,8 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   if (pol.kind == CC_EPS_LEARNED)
     HIP_TRY(hipMemcpyAsync(ws.mlp, pol.mlp.data(), sizeof(float) * CC_MLP_PARAMS, hipMemcpyHostToDevice, s));
 
-  Ws w{};
+  Ws w;
+  std::memset(&w, 0, sizeof(w));  // the bytes (padding included) key the captured round graphs
   w.off = g->roff;
   w.col = g->rcol;
   w.n = n;
@@ -357,14 +406,16 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   } evg{ev0, ev1};
   HIP_TRY(hipEventRecord(ev0, s));
   for (;;) {
-    for (int64_t r = 0; r < group; r++) HIP_TRY(launch_round(w, s, ls));
+    if (int32_t rc = launch_rounds(ws, w, ls, group, s)) return rc;
     launched += group;
     HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->done, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (ws.host_flags[0] || ws.host_flags[1]) break;
     if (ws.host_flags[4] == PHASE_EXACT) ls.exact_seen = 1;
     if (launched > n + 2) return fail(CC_ERR_NO_PROGRESS, "round loop exceeded n+1 rounds");
-    group = group < 64 ? group * 2 : 64;
+    // while the lazy degree search runs, look at the phase every 32 rounds:
+    // its extra kernels stay queued until the host sees the switch
+    group = group * 2 < (ls.exact_seen ? 64 : 32) ? group * 2 : (ls.exact_seen ? 64 : 32);
   }
   HIP_TRY(hipEventRecord(ev1, s));
   if (ws.host_flags[1]) {

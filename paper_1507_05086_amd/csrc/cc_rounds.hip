@@ -698,10 +698,11 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   lb_walk(
       list, work, pk_cnt(lp), pk_work(lp), w.off, w.col, nullptr, info,
       [&](Items &it) {
-        // every center is clustered this round
+        // every center is clustered this round; it goes to the newly list
+        // marked (~v): its row needs no peeling (below)
 #pragma unroll
         for (int k = 0; k < IPT; k++)
-          if (it.vert >> k & 1) stage_push(sb, it.v[k], it.deg[k] > 0 ? it.deg[k] : 1);
+          if (it.vert >> k & 1) stage_push(sb, ~it.v[k], it.deg[k] > 0 ? it.deg[k] : 1);
         bool un[IPT];
 #pragma unroll
         for (int k = 0; k < IPT; k++) un[k] = (it.edge >> k & 1) && unc_bit(w.unc, it.u[k]);
@@ -736,13 +737,25 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   if (threadIdx.x == 0 && s_atom) atomicAdd(&c->sum_atomics, (unsigned long long)s_atom);
 }
 
-// The newly clustered leave the unclustered bitmap; in the exact phase those
-// that still had unclustered neighbours go to the peel list; ClusterWild!
-// conflict marks are counted; the scan tiles of this round are forgotten.
+__device__ inline void hist_add(int *s_hist, int *g_hist, int d, int x) {
+  if (d <= 0) return;
+  if (d < HLDS) atomicAdd(&s_hist[d], x);
+  else atomicAdd(&g_hist[d], x);
+}
+
+// The newly clustered leave the unclustered bitmap; ClusterWild! conflict
+// marks are counted; the scan tiles of this round are forgotten.  In the
+// exact phase the claimed vertices that still had unclustered neighbours go to
+// the peel list.  Centers do not: every unclustered neighbour of a center is
+// claimed in the same round (C4 claims all of them and no two centers are
+// adjacent; ClusterWild!'s active neighbours are centers themselves), so a
+// center's row has nobody left to peel; it only leaves the degree histogram.
 __global__ void __launch_bounds__(BS) k_clear(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
   __shared__ StageBuf<2 * BS> sp;
+  __shared__ int s_hist[HLDS];
+  for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
   stage_init(sp);
   const int64_t nn = pk_cnt(c->n_pack);
   const bool cw = w.algo == ALGO_CW, exact = c->phase == PHASE_EXACT;
@@ -752,13 +765,19 @@ __global__ void __launch_bounds__(BS) k_clear(Ws w) {
   for (int64_t ib = i0; ib < i1; ib += BS) {
     const int64_t i = ib + threadIdx.x;
     if (i < i1) {
-      const int32_t u = w.nlist[i];
+      const int32_t e = w.nlist[i];
+      const bool center = e < 0;
+      const int32_t u = center ? ~e : e;
       atomicAnd(&w.unc[u >> 5], ~(1u << (u & 31)));
       if (cw && w.flag[u]) {
         w.flag[u] = 0;
         conf++;
       }
-      if (exact && w.ub[u] > 0) stage_push(sp, u, (int32_t)(w.off[u + 1] - w.off[u]));
+      if (exact) {
+        const int32_t d = w.ub[u];
+        if (center) hist_add(s_hist, w.hist, d, -1);
+        else if (d > 0) stage_push(sp, u, (int32_t)(w.off[u + 1] - w.off[u]));
+      }
     }
     __syncthreads();
     if (sp.cnt > BS) stage_flush(sp, &c->p_pack, w.plist, w.pwork);
@@ -772,16 +791,16 @@ __global__ void __launch_bounds__(BS) k_clear(Ws w) {
     const int64_t s = wave_sum((int64_t)conf);
     if (lane_id() == 0 && s) atomicAdd(&c->conflicts, (unsigned long long)s);
   }
+  if (exact) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < HLDS; i += BS)
+      if (s_hist[i]) atomicAdd(&w.hist[i], s_hist[i]);
+  }
 }
 
 // --------------------------------------------------------------- peel -----
 // Exact phase: every unclustered neighbour of a newly clustered vertex loses
 // one remaining degree; the degree histogram follows (low bins per workgroup).
-__device__ inline void hist_add(int *s_hist, int *g_hist, int d, int x) {
-  if (d <= 0) return;
-  if (d < HLDS) atomicAdd(&s_hist[d], x);
-  else atomicAdd(&g_hist[d], x);
-}
 
 __global__ void __launch_bounds__(BS) k_peel(Ws w) {
   Ctrl *c = w.ctrl;
