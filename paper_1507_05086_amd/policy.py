@@ -175,6 +175,16 @@ def collect(cc, gh, order, eps_bases, per_run: int, rng, weights=None, label="ro
     return np.array(Xs), np.array(ts)
 
 
+def fold_standardization(w, mu, sd):
+    """Weights for raw features from weights trained on (x - mu) / sd:
+    W1' = W1 / sd (per input), b1' = b1 - W1' mu; the second layer is unchanged."""
+    w = np.asarray(w, np.float64)
+    W1 = w[:384].reshape(64, 6)
+    W1r = W1 / sd
+    b1r = w[384:448] - W1r @ mu
+    return np.concatenate([W1r.ravel(), b1r, w[448:512], w[512:513]])
+
+
 def train_mlp(cc, X, t, steps: int, lr: float, seed: int):
     """Adam on the GPU kernels; returns raw-feature weights (float32[513])."""
     import torch
@@ -190,13 +200,7 @@ def train_mlp(cc, X, t, steps: int, lr: float, seed: int):
     for s in range(1, steps + 1):
         cc.cc_mlp_train_step(p, m, v, xd, td, s, lr, loss=loss)
     final = float(loss.item())
-    w = p.cpu().numpy().astype(np.float64)
-    W1 = w[:384].reshape(64, 6)
-    b1 = w[384:448]
-    W1r = W1 / sd
-    b1r = b1 - W1r @ mu
-    out = np.concatenate([W1r.ravel(), b1r, w[448:512], w[512:513]]).astype(np.float32)
-    return out, final
+    return fold_standardization(p.cpu().numpy(), mu, sd).astype(np.float32), final
 
 
 def save(weights, meta, path=WEIGHTS):
