@@ -167,8 +167,9 @@ __device__ __forceinline__ int rows_pass(const Grp<G> &g, const int16_t *list, i
   chunk = (chunk + 63) & ~63;
   const int c0 = min(total, w * chunk), c1 = min(total, c0 + chunk);
   if (c0 < c1) {
-    // lo: the last row whose prefix is <= c0 (the same search in every lane)
-    int lo = 0, hi = cnt;
+    // lo: the last row whose prefix is <= c0 (the same search in every lane);
+    // row 0 already satisfies the invariant below when c0 = 0
+    int lo = 0, hi = c0 > 0 ? cnt : 1;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (s.pref[mid] <= c0) lo = mid;
@@ -422,10 +423,12 @@ __device__ __forceinline__ void solve_graph(const Grp<G> &g, const BatchArgs &a,
     });
     if (g.tid == 0) st.claim += (unsigned long long)t_claim;
     const int nn = *nn_ptr;
-    // the newly clustered leave; their unclustered neighbours lose one degree
+    // the newly clustered leave; the unclustered neighbours of the claimed
+    // ones lose one degree.  Centers (nlist[0, nc)) have none left: every
+    // unclustered neighbour of a center was claimed this round.
     for (int i = g.tid; i < nn; i += G) s.fl[s.nlist[i]] = 0;
     g.sync();
-    const int t_peel = rows_pass<G, K, W>(g, s.nlist, nn, s, col0, rs, [&](int, int32_t, int32_t u) {
+    const int t_peel = rows_pass<G, K, W>(g, s.nlist + nc, nn - nc, s, col0, rs, [&](int, int32_t, int32_t u) {
       if (s.fl[u] & F_UNC) {
         atomicSub(&s.lw[u], 1u);
         st.atom++;
