@@ -392,7 +392,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     return fail(CC_ERR_NOT_PERMUTATION, "order is not a permutation of 0..n-1");
   if (ws.host_flags[1]) return fail(CC_ERR_DEVICE, "device error during initialisation");
 
-  LaunchShape ls{256, 2048, 1024, 0, 0};
+  LaunchShape ls{256, 1024, 512, 0, 0};
   int64_t launched = 0, group = 4;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   HIP_TRY(hipEventCreate(&ev0));

@@ -91,6 +91,9 @@ struct Ctrl {
   unsigned int lvl_cnt[NLVL];
   // run totals
   unsigned long long sum_elect, sum_claim, sum_rescan, sum_peel, sum_blocked, sum_atomics;
+  // per-round statistics spread over 64 slots (slot = workgroup mod 64): one
+  // address taken by every workgroup would serialise their atomics
+  unsigned long long spread_atom[64], spread_conf[64];
 };
 
 // A listed vertex's row: start of its adjacency in col, its degree and its

@@ -734,7 +734,7 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
         if (sb.cnt > CLAIM_CAP - 2 * TW) stage_flush(sb, &c->n_pack, w.nlist, w.nwork);
       });
   stage_flush(sb, &c->n_pack, w.nlist, w.nwork);
-  if (threadIdx.x == 0 && s_atom) atomicAdd(&c->sum_atomics, (unsigned long long)s_atom);
+  if (threadIdx.x == 0 && s_atom) atomicAdd(&c->spread_atom[blockIdx.x & 63], (unsigned long long)s_atom);
 }
 
 __device__ inline void hist_add(int *s_hist, int *g_hist, int d, int x) {
@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(BS) k_clear(Ws w) {
     w.tstat[t] = 0;
   if (cw) {
     const int64_t s = wave_sum((int64_t)conf);
-    if (lane_id() == 0 && s) atomicAdd(&c->conflicts, (unsigned long long)s);
+    if (lane_id() == 0 && s) atomicAdd(&c->spread_conf[blockIdx.x & 63], (unsigned long long)s);
   }
   if (exact) {
     __syncthreads();
@@ -832,7 +832,7 @@ __global__ void __launch_bounds__(BS) k_peel(Ws w) {
   __syncthreads();
   for (int i = threadIdx.x; i < HLDS; i += BS)
     if (s_hist[i]) atomicAdd(&w.hist[i], s_hist[i]);
-  if (threadIdx.x == 0 && s_atom) atomicAdd(&c->sum_atomics, (unsigned long long)s_atom);
+  if (threadIdx.x == 0 && s_atom) atomicAdd(&c->spread_atom[blockIdx.x & 63], (unsigned long long)s_atom);
 }
 
 // -------------------------------------------------------------- close -----
@@ -842,6 +842,17 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
   const long long now = (long long)wall_clock64();
+  {  // fold the spread statistics of the round
+    const int l = lane_id();
+    const unsigned long long sa = (unsigned long long)wave_sum((int64_t)c->spread_atom[l]);
+    const unsigned long long sc = (unsigned long long)wave_sum((int64_t)c->spread_conf[l]);
+    c->spread_atom[l] = 0;
+    c->spread_conf[l] = 0;
+    if (l == 0) {
+      c->sum_atomics += sa;
+      c->conflicts += sc;
+    }
+  }
   long long n_rem = 0, delta = 0, round = 0;
   int done = 0;
   float fconf = 0.f, fclaim = 0.f, feps = 0.f;
