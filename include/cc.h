@@ -166,9 +166,11 @@ CC_API int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double ep
  * from a queue (largest first), keeps its vertex state in LDS and runs the
  * whole round loop of Algorithm 2 on it with the fixed eps rule, then takes
  * the next graph.  Graphs of at most `wave_max_n` vertices run on a single
- * wave (several per workgroup); larger ones on a whole workgroup of `block`
- * threads.  Each graph may hold at most CC_BATCH_MAX_N vertices (the LDS of
- * one workgroup).  Labels are per graph, local ids; per-graph rounds come
+ * wave (several per workgroup); with block >= 512, graphs of at most
+ * `quad_max_n` vertices run on a sub-group of 4 waves (block / 256 graphs
+ * per workgroup); larger ones on the whole workgroup of `block` threads.
+ * Each graph may hold at most CC_BATCH_MAX_N vertices (the LDS of one
+ * workgroup).  Labels are per graph, local ids; per-graph rounds come
  * back in cc_run_stats.graph_rounds; no per-round trace is recorded.  A
  * batch run with a LEARNED or TRACE policy set fails with CC_ERR_POLICY.
  */
@@ -178,6 +180,9 @@ enum cc_algo { CC_ALGO_C4 = 0, CC_ALGO_CLUSTERWILD = 1 };
 typedef struct cc_batch_config {
   int32_t block;      /* threads per workgroup: 256, 512 or 1024 */
   int32_t wave_max_n; /* graphs with n_g <= wave_max_n run one per wave (0: none) */
+  int32_t quad_max_n; /* block >= 512: graphs with wave_max_n < n_g <= quad_max_n run one
+                         per 4-wave sub-group (0: none) */
+  int32_t reserved;   /* 0 */
   double ms;          /* cc_batch_autotune: best measured time of one launch */
 } cc_batch_config;
 
@@ -191,9 +196,9 @@ typedef struct cc_batch_config {
 CC_API int32_t cc_batch_set_config(cc_graph *g, const cc_batch_config *cfg);
 
 /*
- * Time every launch shape that fits (block in {256, 512, 1024} x a ladder of
- * wave_max_n values) on this batch with `algo` (cc_algo), `order` and `eps`
- * (as for cc_c4; flags: CC_INPUT_ON_DEVICE only), keep the fastest for the
+ * Time every launch shape that fits (block in {256, 512, 1024} x ladders of
+ * wave_max_n and quad_max_n values) on this batch with `algo` (cc_algo),
+ * `order` and `eps` (as for cc_c4; flags: CC_INPUT_ON_DEVICE only), keep the fastest for the
  * handle and for its size class, and return it in *best (may be NULL).
  * Runs the batch three times per shape; labels are not returned.
  */

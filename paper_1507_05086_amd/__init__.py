@@ -77,7 +77,8 @@ class _RunStats(ctypes.Structure):
 
 
 class _BatchConfig(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("wave_max_n", ctypes.c_int32), ("ms", ctypes.c_double)]
+    _fields_ = [("block", ctypes.c_int32), ("wave_max_n", ctypes.c_int32), ("quad_max_n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 def _load():
@@ -273,13 +274,15 @@ def cc_cost(graph: Graph, labels, stream=None) -> np.ndarray:
 class BatchConfig:
     block: int
     wave_max_n: int
+    quad_max_n: int = 0
     ms: float = 0.0
 
 
-def cc_batch_set_config(graph: Graph, block: int, wave_max_n: int):
+def cc_batch_set_config(graph: Graph, block: int, wave_max_n: int, quad_max_n: int = 0):
     """Fix a batch's launch shape: `block` threads per workgroup, graphs of at
-    most `wave_max_n` vertices one per wave."""
-    c = _BatchConfig(int(block), int(wave_max_n), 0.0)
+    most `wave_max_n` vertices one per wave, then (block >= 512) graphs of at
+    most `quad_max_n` vertices one per 4-wave sub-group."""
+    c = _BatchConfig(int(block), int(wave_max_n), int(quad_max_n), 0, 0.0)
     _check(_lib.cc_batch_set_config(graph.handle, ctypes.byref(c)))
 
 
@@ -289,7 +292,7 @@ def cc_batch_autotune(graph: Graph, order, algo: int = CC_ALGO_C4, eps: float = 
     c = _BatchConfig()
     _check(_lib.cc_batch_autotune(graph.handle, int(algo), po, float(eps), CC_INPUT_ON_DEVICE if odev else 0,
                                   _stream(stream, order), ctypes.byref(c)))
-    return BatchConfig(c.block, c.wave_max_n, c.ms)
+    return BatchConfig(c.block, c.wave_max_n, c.quad_max_n, c.ms)
 
 
 def _dev(t, name):

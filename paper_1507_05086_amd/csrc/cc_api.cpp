@@ -100,8 +100,8 @@ struct BatchState {
   int32_t *rounds = nullptr;
   unsigned long long *stat = nullptr;
   int *err = nullptr;
-  int q_block = 0, q_wave = -1;  // shape the uploaded queue was built for
-  int n_big = 0, cap_big = 0, cap_wave = 0;
+  int q_block = 0, q_wave = -1, q_quad = -1;  // shape the uploaded queue was built for
+  int n_big = 0, n_quad = 0, cap_big = 0, cap_quad = 0, cap_wave = 0;
   bool has_cfg = false;          // shape fixed by cc_batch_set_config / cc_batch_autotune
   cc_batch_config cfg{};
 };
@@ -501,23 +501,30 @@ SizeClass size_class(const cc_graph *g, int arch) {
   return SizeClass{arch, ilog2_ceil(g->num_graphs), ilog2_ceil(mx + 1), ilog2_ceil(med + 1)};
 }
 
+// Tier of a graph under a shape: 0 workgroup, 1 sub-group of 4 waves, 2 wave.
+int tier_of(int64_t n, const cc_batch_config &c) {
+  if (n <= c.wave_max_n) return 2;
+  if (c.block > 256 && n <= c.quad_max_n) return 1;
+  return 0;
+}
+
 // LDS (bytes of dynamic shared memory) a shape needs for this batch; sets the
-// slot capacities: the largest graph of each queue.
-size_t shape_lds(const cc_graph *g, int block, int wave_max_n, int *cap_big, int *cap_wave, int *n_big) {
-  int cb = 0, cw = 0, nb = 0;
+// slot capacities: the largest graph of each tier.
+size_t shape_lds(const cc_graph *g, const cc_batch_config &c, int *cap_big, int *cap_quad, int *cap_wave, int *n_big,
+                 int *n_quad) {
+  int cap[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
   for (int32_t i = 0; i < g->num_graphs; i++) {
     const int n = (int)graph_n(g, i);
-    if (n > wave_max_n) {
-      cb = std::max(cb, n);
-      nb++;
-    } else {
-      cw = std::max(cw, n);
-    }
+    const int t = tier_of(n, c);
+    cap[t] = std::max(cap[t], n);
+    cnt[t]++;
   }
-  if (cap_big) *cap_big = cb;
-  if (cap_wave) *cap_wave = cw;
-  if (n_big) *n_big = nb;
-  return batched_lds_bytes(block, cb, cw);
+  if (cap_big) *cap_big = cap[0];
+  if (cap_quad) *cap_quad = cap[1];
+  if (cap_wave) *cap_wave = cap[2];
+  if (n_big) *n_big = cnt[0];
+  if (n_quad) *n_quad = cnt[1];
+  return batched_lds_bytes(c.block, cap[0], cap[1], cap[2]);
 }
 
 // Static LDS of the batched kernel (graph id, scan scratch, 256 B of window
@@ -527,10 +534,11 @@ constexpr int kBatchStaticLds = 4608;
 int32_t check_shape(const cc_graph *g, const cc_batch_config &c) {
   if (c.block != 256 && c.block != 512 && c.block != 1024)
     return fail(CC_ERR_INVALID_ARG, "batch block must be 256, 512 or 1024");
-  if (c.wave_max_n < 0) return fail(CC_ERR_INVALID_ARG, "wave_max_n must be >= 0");
+  if (c.wave_max_n < 0 || c.quad_max_n < 0) return fail(CC_ERR_INVALID_ARG, "wave_max_n and quad_max_n must be >= 0");
+  if (c.reserved != 0) return fail(CC_ERR_INVALID_ARG, "cc_batch_config.reserved must be 0");
   int arch = 0, max_lds = 0;
   if (int32_t rc = device_arch(&arch, &max_lds)) return rc;
-  const size_t lds = shape_lds(g, c.block, c.wave_max_n, nullptr, nullptr, nullptr);
+  const size_t lds = shape_lds(g, c, nullptr, nullptr, nullptr, nullptr, nullptr);
   if (lds + kBatchStaticLds > (size_t)max_lds)
     return fail(CC_ERR_INVALID_ARG, "batch shape needs " + std::to_string(lds) + " B of LDS per workgroup; the device has " +
                                         std::to_string(max_lds));
@@ -539,7 +547,7 @@ int32_t check_shape(const cc_graph *g, const cc_batch_config &c) {
 
 cc_batch_config default_shape(const cc_graph *g) {
   // one wave per graph while four wave slots fit beside the largest graph's slot
-  cc_batch_config c{256, 0, 0.0};
+  cc_batch_config c{256, 0, 0, 0, 0.0};
   int64_t mx = 0;
   for (int32_t i = 0; i < g->num_graphs; i++) mx = std::max(mx, graph_n(g, i));
   c.wave_max_n = (int)std::min<int64_t>(512, std::max<int64_t>(64, mx / 4));
@@ -550,32 +558,34 @@ int32_t ensure_batch(cc_graph *g) {
   BatchState &b = g->bs;
   if (b.queue) return CC_OK;
   HIP_TRY(dalloc(&b.queue, (size_t)g->num_graphs));
-  HIP_TRY(dalloc(&b.heads, 2));
+  HIP_TRY(dalloc(&b.heads, 3));
   HIP_TRY(dalloc(&b.rounds, (size_t)g->num_graphs));
   HIP_TRY(dalloc(&b.stat, 4));
   HIP_TRY(dalloc(&b.err, 1));
   return CC_OK;
 }
 
-// Queue of graph ids: graphs above wave_max_n first, then the rest; each part
-// in decreasing order of work (entries + vertices), so the persistent groups
-// finish together (longest-processing-time-first).
-int32_t build_queue(cc_graph *g, int block, int wave_max_n, hipStream_t s) {
+// Queue of graph ids: the workgroup tier, then the sub-group tier, then the
+// wave tier; each part in decreasing order of work (entries + vertices), so
+// the persistent groups finish together (longest-processing-time-first).
+int32_t build_queue(cc_graph *g, const cc_batch_config &c, hipStream_t s) {
   BatchState &b = g->bs;
-  if (b.q_block == block && b.q_wave == wave_max_n) return CC_OK;
-  std::vector<int32_t> big, small;
-  for (int32_t i = 0; i < g->num_graphs; i++) (graph_n(g, i) > wave_max_n ? big : small).push_back(i);
+  if (b.q_block == c.block && b.q_wave == c.wave_max_n && b.q_quad == c.quad_max_n) return CC_OK;
+  std::vector<int32_t> part[3];
+  for (int32_t i = 0; i < g->num_graphs; i++) part[tier_of(graph_n(g, i), c)].push_back(i);
   auto work = [&](int32_t i) { return 2 * g->m_per_graph[(size_t)i] + graph_n(g, i); };
   auto by_work = [&](int32_t x, int32_t y) { return work(x) != work(y) ? work(x) > work(y) : x < y; };
-  std::sort(big.begin(), big.end(), by_work);
-  std::sort(small.begin(), small.end(), by_work);
-  std::vector<int32_t> q(big);
-  q.insert(q.end(), small.begin(), small.end());
+  std::vector<int32_t> q;
+  for (auto &p : part) {
+    std::sort(p.begin(), p.end(), by_work);
+    q.insert(q.end(), p.begin(), p.end());
+  }
   HIP_TRY(hipMemcpyAsync(b.queue, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  shape_lds(g, block, wave_max_n, &b.cap_big, &b.cap_wave, &b.n_big);
-  b.q_block = block;
-  b.q_wave = wave_max_n;
+  shape_lds(g, c, &b.cap_big, &b.cap_quad, &b.cap_wave, &b.n_big, &b.n_quad);
+  b.q_block = c.block;
+  b.q_wave = c.wave_max_n;
+  b.q_quad = c.quad_max_n;
   return CC_OK;
 }
 
@@ -583,20 +593,21 @@ int32_t build_queue(cc_graph *g, int block, int wave_max_n, hipStream_t s) {
 int32_t launch_batch(cc_graph *g, int algo, const int32_t *d_order, int64_t eps_q, int32_t *d_labels,
                      const cc_batch_config &c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   BatchState &b = g->bs;
-  if (int32_t rc = build_queue(g, c.block, c.wave_max_n, s)) return rc;
-  const size_t lds = batched_lds_bytes(c.block, b.cap_big, b.cap_wave);
+  if (int32_t rc = build_queue(g, c, s)) return rc;
+  const size_t lds = batched_lds_bytes(c.block, b.cap_big, b.cap_quad, b.cap_wave);
   int grid = 0;
   HIP_TRY(batched_max_grid(c.block, lds, &grid));
   if (grid < 1) return fail(CC_ERR_DEVICE, "batched kernel does not fit on a compute unit");
-  const int waves = c.block / 64;
-  const int64_t nsmall = g->num_graphs - b.n_big;
-  const int64_t need = std::max<int64_t>(1, b.n_big + (nsmall + waves - 1) / waves);
+  const int waves = c.block / 64, quads = c.block / 256;
+  const int64_t nsmall = g->num_graphs - b.n_big - b.n_quad;
+  const int64_t need =
+      std::max<int64_t>(1, b.n_big + (b.n_quad + quads - 1) / quads + (nsmall + waves - 1) / waves);
   if (need < grid) grid = (int)need;
-  HIP_TRY(hipMemsetAsync(b.heads, 0, 2 * sizeof(unsigned), s));
+  HIP_TRY(hipMemsetAsync(b.heads, 0, 3 * sizeof(unsigned), s));
   HIP_TRY(hipMemsetAsync(b.stat, 0, 4 * sizeof(unsigned long long), s));
   HIP_TRY(hipMemsetAsync(b.err, 0, sizeof(int), s));
-  BatchLaunch bl{g->off, g->col, g->vtx_ptr, d_order, d_labels, b.queue, b.n_big, g->num_graphs, b.cap_big,
-                 b.cap_wave, b.heads, b.rounds, b.stat, b.err, algo, eps_q, c.block, grid};
+  BatchLaunch bl{g->off, g->col, g->vtx_ptr, d_order, d_labels, b.queue, b.n_big, b.n_quad, g->num_graphs,
+                 b.cap_big, b.cap_quad, b.cap_wave, b.heads, b.rounds, b.stat, b.err, algo, eps_q, c.block, grid};
   if (ev0) HIP_TRY(hipEventRecord(ev0, s));
   HIP_TRY(launch_batched(bl, s));
   if (ev1) HIP_TRY(hipEventRecord(ev1, s));
@@ -700,6 +711,7 @@ int32_t autotune_batch(cc_graph *g, int algo, const int32_t *order, double eps, 
   int64_t mx = 0;
   for (int32_t i = 0; i < g->num_graphs; i++) mx = std::max(mx, graph_n(g, i));
   static const int kWave[] = {0, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 7168};
+  static const int kQuad[] = {0, 512, 768, 1024, 1280, 1536, 1792, 2048, 3072, 4096};
   static const int kBlock[] = {256, 512, 1024};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   HIP_TRY(hipEventCreate(&ev0));
@@ -711,29 +723,34 @@ int32_t autotune_batch(cc_graph *g, int algo, const int32_t *order, double eps, 
       (void)hipEventDestroy(b);
     }
   } evg{ev0, ev1};
-  cc_batch_config top{0, 0, 1e300};
+  cc_batch_config top{0, 0, 0, 0, 1e300};
   for (int blk : kBlock) {
-    int prev_cap = -1;
+    int prev_split = -1;
     for (int wv : kWave) {
       if (wv > 0 && wv / 2 >= mx) break;  // every graph already runs on a wave
-      cc_batch_config c{blk, wv, 0.0};
-      int cb = 0, cw = 0, nb = 0;
-      const size_t lds = shape_lds(g, blk, wv, &cb, &cw, &nb);
-      if (lds + kBatchStaticLds > (size_t)max_lds) continue;
-      if (cw == prev_cap) continue;  // same split as the previous rung
-      prev_cap = cw;
-      double t = 1e300;
-      for (int rep = 0; rep < 3; rep++) {
-        if (int32_t rc = launch_batch(g, algo, d_order, eps_q, g->ws.label_buf, c, s, ev0, ev1)) return rc;
-        int herr = 0;
-        HIP_TRY(hipMemcpyAsync(&herr, g->bs.err, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (herr) return batch_error(herr);
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
-        if (rep > 0) t = std::min(t, (double)ms);  // first run warms caches
+      for (int qd : kQuad) {
+        if (qd != 0 && (blk == 256 || qd <= wv)) continue;
+        if (qd > 0 && qd / 2 >= mx) break;
+        cc_batch_config c{blk, wv, qd, 0, 0.0};
+        int cb = 0, cq = 0, cw = 0, nb = 0, nq = 0;
+        const size_t lds = shape_lds(g, c, &cb, &cq, &cw, &nb, &nq);
+        if (lds + kBatchStaticLds > (size_t)max_lds) continue;
+        const int split = cw * 65536 + nq;  // same tiers as the previous candidate: skip
+        if (qd == 0 && split == prev_split) continue;
+        if (qd == 0) prev_split = split;
+        double t = 1e300;
+        for (int rep = 0; rep < 3; rep++) {
+          if (int32_t rc = launch_batch(g, algo, d_order, eps_q, g->ws.label_buf, c, s, ev0, ev1)) return rc;
+          int herr = 0;
+          HIP_TRY(hipMemcpyAsync(&herr, g->bs.err, sizeof(int), hipMemcpyDeviceToHost, s));
+          HIP_TRY(hipStreamSynchronize(s));
+          if (herr) return batch_error(herr);
+          float ms = 0.f;
+          HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+          if (rep > 0) t = std::min(t, (double)ms);  // first run warms caches
+        }
+        if (t < top.ms) top = cc_batch_config{blk, wv, qd, 0, t};
       }
-      if (t < top.ms) top = cc_batch_config{blk, wv, t};
     }
   }
   if (top.block == 0) return fail(CC_ERR_INVALID_ARG, "no batch shape fits the device's LDS");

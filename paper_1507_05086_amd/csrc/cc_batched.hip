@@ -24,44 +24,84 @@ enum : uint8_t { F_UNC = 1, F_ACT = 2, F_CEN = 4, F_NON = 8, F_BLK = 16, F_MC = 
 constexpr uint32_t INF16 = 0x7FFF;
 __device__ inline uint32_t lw_pack(uint32_t lab, uint32_t deg) { return (lab << 16) | deg; }
 
-// A group of G threads working on one graph (G = 64: one wave; G = block).
-template <int G>
+// Barrier of a sub-group of nw waves inside a workgroup (sense reversal on a
+// generation counter in LDS).  Every wave of a workgroup is resident, so the
+// waiting lanes always see the last arrival.
+struct SubBar {
+  int count, gen;
+};
+
+__device__ __forceinline__ void sub_sync(SubBar *b, int nw) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (lane_id() == 0) {
+    const int g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int arrived = __hip_atomic_fetch_add(&b->count, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (arrived == nw - 1) {
+      __hip_atomic_store(&b->count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_store(&b->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == g)
+        __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// A group of G threads working on one graph: one wave (G = 64), a sub-group
+// of G / 64 waves of a larger workgroup (SUB), or the whole workgroup.
+template <int G, bool SUB = false>
 struct Grp {
-  int tid;
+  static constexpr int size = G;
+  int tid;      // 0 .. G-1
   int64_t *sh;  // G/64 + 1 slots of scratch
-  __device__ void sync() const {
+  SubBar *bar;  // SUB only
+  int wave0;    // first wave of the group in the workgroup
+  __device__ __forceinline__ int wave() const { return G == 64 ? 0 : wave_id() - wave0; }
+  __device__ __forceinline__ void sync() const {
     if (G == 64) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else if (SUB) {
+      sub_sync(bar, G / 64);
     } else {
       __syncthreads();
     }
   }
   // exclusive scan; *tot = sum over the group
-  __device__ int64_t scan(int64_t x, int64_t *tot) const {
+  __device__ __forceinline__ int64_t scan(int64_t x, int64_t *tot) const {
+    const int64_t inc = wave_incl_scan(x);
     if (G == 64) {
-      const int64_t inc = wave_incl_scan(x);
       *tot = __shfl(inc, 63, 64);
       return inc - x;
     }
-    return wg_excl_scan<G>(x, tot, sh);
+    if (lane_id() == 63) sh[wave()] = inc;
+    sync();
+    int64_t base = 0, t = 0;
+    for (int w = 0; w < G / 64; w++) {
+      if (w < wave()) base += sh[w];
+      t += sh[w];
+    }
+    sync();
+    *tot = t;
+    return base + inc - x;
   }
-  __device__ int64_t max(int64_t x) const {
+  __device__ __forceinline__ int64_t max(int64_t x) const {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
       const int64_t y = __shfl_xor(x, d, 64);
       x = y > x ? y : x;
     }
     if (G == 64) return x;
-    if (lane_id() == 0) sh[wave_id()] = x;
-    __syncthreads();
+    if (lane_id() == 0) sh[wave()] = x;
+    sync();
     int64_t m = sh[0];
     for (int i = 1; i < G / 64; i++) m = sh[i] > m ? sh[i] : m;
-    __syncthreads();
+    sync();
     return m;
   }
-  __device__ bool any(bool p) const { return max(p ? 1 : 0) != 0; }
+  __device__ __forceinline__ bool any(bool p) const { return max(p ? 1 : 0) != 0; }
 };
 
 __device__ inline void wave_sync() {
@@ -81,10 +121,11 @@ struct BatchArgs {
   const int32_t *order;    // per graph local permutation (concatenated)
   int32_t *labels;         // out: local center ids
   const int32_t *queue;    // graph ids, large-graph queue first, each part most work first
-  int32_t n_big;           // queue[0, n_big): one graph per workgroup; rest: one per wave
+  int32_t n_big;           // queue[0, n_big): one graph per workgroup
+  int32_t n_quad;          // queue[n_big, n_big + n_quad): one per 4-wave sub-group; rest: one per wave
   int32_t num_graphs;
-  int32_t cap_big, cap_wave;  // LDS vertex capacity of a workgroup slot / a wave slot
-  unsigned *heads;         // [2] queue heads
+  int32_t cap_big, cap_quad, cap_wave;  // LDS vertex capacity of a workgroup / sub-group / wave slot
+  unsigned *heads;         // [3] queue heads
   int32_t *rounds;         // out: rounds per graph
   unsigned long long *stat;  // [4]: elect, claim, peel entries, atomics
   int *err;
@@ -140,9 +181,10 @@ __device__ inline long long bt_batch(long long eps_q, long long n_rem, long long
 // is streamed with K loads in flight; otherwise up to W windows of 64 entries
 // have their rows located (LDS only) before their loads are issued together.
 // Returns the number of entries walked.
-template <int G, int K, int W, class F>
-__device__ __forceinline__ int rows_pass(const Grp<G> &g, const int16_t *list, int cnt, Slot &s, const int32_t *col0,
+template <class GR, int K, int W, class F>
+__device__ __forceinline__ int rows_pass(const GR &g, const int16_t *list, int cnt, Slot &s, const int32_t *col0,
                                 int *rs, F &&f) {
+  constexpr int G = GR::size;
   int carry = 0;
   for (int i0 = 0; i0 < cnt; i0 += G) {
     const int i = i0 + g.tid;
@@ -162,7 +204,7 @@ __device__ __forceinline__ int rows_pass(const Grp<G> &g, const int16_t *list, i
   if (total == 0) return 0;
   constexpr int NW = G / 64;
   const int lane = lane_id();
-  const int w = NW == 1 ? 0 : wave_id();
+  const int w = NW == 1 ? 0 : g.wave();
   int chunk = (total + NW - 1) / NW;
   chunk = (chunk + 63) & ~63;
   const int c0 = min(total, w * chunk), c1 = min(total, c0 + chunk);
@@ -252,8 +294,9 @@ __device__ __forceinline__ int rows_pass(const Grp<G> &g, const int16_t *list, i
 
 // Inlined into the kernel so that every Slot pointer is known to address LDS
 // (an out-of-line call would turn them into generic pointers).
-template <int G>
-__device__ __forceinline__ void solve_graph(const Grp<G> &g, const BatchArgs &a, int gi, int cap, Slot &s, int *rs, BStats &st) {
+template <class GR>
+__device__ __forceinline__ void solve_graph(const GR &g, const BatchArgs &a, int gi, int cap, Slot &s, int *rs, BStats &st) {
+  constexpr int G = GR::size;
   const int64_t v0 = a.vtx_ptr[gi];
   const int n = (int)(a.vtx_ptr[gi + 1] - v0);
   if (n > cap) {  // the host sizes the slots; never taken
@@ -334,7 +377,7 @@ __device__ __forceinline__ void solve_graph(const Grp<G> &g, const BatchArgs &a,
     int nc = 0;
     if (c4) {
       // blocked: an earlier-ranked active neighbour
-      const int t_elect = rows_pass<G, K, W>(g, s.alist, B, s, col0, rs, [&](int, int32_t av, int32_t u) {
+      const int t_elect = rows_pass<GR, K, W>(g, s.alist, B, s, col0, rs, [&](int, int32_t av, int32_t u) {
         if ((s.fl[u] & F_ACT) && s.rank[u] < s.rank[av]) s.fl[av] |= F_BLK;
       });
       if (g.tid == 0) st.elect += (unsigned long long)t_elect;
@@ -362,7 +405,7 @@ __device__ __forceinline__ void solve_graph(const Grp<G> &g, const BatchArgs &a,
         }
         g.sync();
         if (nb == 0) break;
-        const int t_res = rows_pass<G, K, W>(g, s.nlist, nb, s, col0, rs, [&](int, int32_t av, int32_t u) {
+        const int t_res = rows_pass<GR, K, W>(g, s.nlist, nb, s, col0, rs, [&](int, int32_t av, int32_t u) {
           const uint8_t fu = s.fl[u];
           if ((fu & F_ACT) && s.rank[u] < s.rank[av]) {
             const unsigned bit = (fu & F_CEN) ? (unsigned)F_MC : ((fu & F_NON) ? 0u : (unsigned)F_MU);
@@ -410,7 +453,7 @@ __device__ __forceinline__ void solve_graph(const Grp<G> &g, const BatchArgs &a,
       s.nlist[atomicAdd(nn_ptr, 1)] = (int16_t)cv;
     }
     g.sync();
-    const int t_claim = rows_pass<G, K, W>(g, s.alist, nc, s, col0, rs, [&](int, int32_t cv, int32_t u) {
+    const int t_claim = rows_pass<GR, K, W>(g, s.alist, nc, s, col0, rs, [&](int, int32_t cv, int32_t u) {
       const uint8_t fu = s.fl[u];
       if (!(fu & F_UNC) || (fu & F_CEN)) return;
       if (!c4 && (fu & F_ACT)) return;  // ClusterWild! claims Gamma(c) \ A
@@ -428,7 +471,7 @@ __device__ __forceinline__ void solve_graph(const Grp<G> &g, const BatchArgs &a,
     // unclustered neighbour of a center was claimed this round.
     for (int i = g.tid; i < nn; i += G) s.fl[s.nlist[i]] = 0;
     g.sync();
-    const int t_peel = rows_pass<G, K, W>(g, s.nlist + nc, nn - nc, s, col0, rs, [&](int, int32_t, int32_t u) {
+    const int t_peel = rows_pass<GR, K, W>(g, s.nlist + nc, nn - nc, s, col0, rs, [&](int, int32_t, int32_t u) {
       if (s.fl[u] & F_UNC) {
         atomicSub(&s.lw[u], 1u);
         st.atom++;
@@ -448,48 +491,76 @@ __device__ __forceinline__ void solve_graph(const Grp<G> &g, const BatchArgs &a,
   if (n_rem > 0 && g.tid == 0) atomicCAS(a.err, 0, ERR_NO_PROGRESS);
 }
 
+constexpr int QG = 256;  // threads of a sub-group (4 waves)
+
 template <int T>
 __global__ void __launch_bounds__(T) k_batched(BatchArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   BStats st{0, 0, 0, 0};
-  __shared__ int s_gi;
+  constexpr int NQ = T / QG > 0 ? T / QG : 1;
+  __shared__ int s_gi[NQ];
   __shared__ int64_t sh[T / 64 + 1];
+  __shared__ int64_t shq[NQ][QG / 64 + 1];
+  __shared__ SubBar sbar[NQ];
   __shared__ int rsb[T / 64][64];
   int *rs = rsb[wave_id()];
+  if (threadIdx.x < NQ) sbar[threadIdx.x] = SubBar{0, 0};
+  __syncthreads();
   // phase 1: large graphs, one per workgroup
-  Grp<T> gw{(int)threadIdx.x, sh};
+  Grp<T> gw{(int)threadIdx.x, sh, nullptr, 0};
   Slot sl;
   sl.carve(lds, a.cap_big);
   for (;;) {
     if (threadIdx.x == 0) {
       const unsigned q = atomicAdd(&a.heads[0], 1u);
-      s_gi = (int)q < a.n_big ? a.queue[q] : -1;
+      s_gi[0] = (int)q < a.n_big ? a.queue[q] : -1;
     }
     __syncthreads();
-    const int gi = s_gi;
+    const int gi = s_gi[0];
     __syncthreads();
     if (gi < 0) break;
-    solve_graph<T>(gw, a, gi, a.cap_big, sl, rs, st);
+    solve_graph(gw, a, gi, a.cap_big, sl, rs, st);
     __syncthreads();
   }
-  // phase 2: small graphs, one per wave
-  Grp<64> gv{lane_id(), nullptr};
+  // phase 2: mid-size graphs, one per sub-group of 4 waves (workgroups of 512+)
+  if (T > QG && a.n_quad > 0) {
+    const int sg = (int)threadIdx.x / QG;
+    Grp<QG, true> gq{(int)threadIdx.x % QG, shq[sg], &sbar[sg], sg * (QG / 64)};
+    Slot sq;
+    sq.carve(lds + (size_t)sg * Slot::bytes(a.cap_quad), a.cap_quad);
+    for (;;) {
+      if (gq.tid == 0) {
+        const unsigned q = atomicAdd(&a.heads[2], 1u);
+        s_gi[sg] = (int)q < a.n_quad ? a.queue[a.n_big + q] : -1;
+      }
+      gq.sync();
+      const int gi = s_gi[sg];
+      gq.sync();
+      if (gi < 0) break;
+      solve_graph(gq, a, gi, a.cap_quad, sq, rs, st);
+      gq.sync();
+    }
+    __syncthreads();
+  }
+  // phase 3: small graphs, one per wave
+  Grp<64> gv{lane_id(), nullptr, nullptr, 0};
   Slot sv;
   sv.carve(lds + (size_t)wave_id() * Slot::bytes(a.cap_wave), a.cap_wave);
-  const int nsmall = a.num_graphs - a.n_big;
+  const int n0 = a.n_big + a.n_quad, nsmall = a.num_graphs - n0;
   for (;;) {
     int q = 0;
     if (lane_id() == 0) q = (int)atomicAdd(&a.heads[1], 1u);
     q = __shfl(q, 0, 64);
     if (q >= nsmall) break;
-    solve_graph<64>(gv, a, a.queue[a.n_big + q], a.cap_wave, sv, rs, st);
+    solve_graph(gv, a, a.queue[n0 + q], a.cap_wave, sv, rs, st);
   }
   // statistics: one reduction per workgroup, one atomic per counter
   __syncthreads();
   unsigned long long v4[4] = {st.elect, st.claim, st.peel, st.atom};
   for (int k = 0; k < 4; k++) {
     int64_t tot;
-    wg_excl_scan<T>((int64_t)v4[k], &tot, sh);
+    const int64_t pre = gw.scan((int64_t)v4[k], &tot);
+    (void)pre;
     if (threadIdx.x == 0 && tot) atomicAdd(&a.stat[k], (unsigned long long)tot);
   }
 }
@@ -502,9 +573,9 @@ static hipError_t allow_lds(int block, size_t lds) {
 }
 
 hipError_t launch_batched(const BatchLaunch &bl, hipStream_t s) {
-  BatchArgs a{bl.off, bl.col, bl.vtx_ptr, bl.order, bl.labels, bl.queue, bl.n_big, bl.num_graphs,
-              bl.cap_big, bl.cap_wave, bl.heads, bl.rounds, bl.stat, bl.err, bl.algo, bl.eps_q};
-  const size_t lds = batched_lds_bytes(bl.block, bl.cap_big, bl.cap_wave);
+  BatchArgs a{bl.off, bl.col, bl.vtx_ptr, bl.order, bl.labels, bl.queue, bl.n_big, bl.n_quad, bl.num_graphs,
+              bl.cap_big, bl.cap_quad, bl.cap_wave, bl.heads, bl.rounds, bl.stat, bl.err, bl.algo, bl.eps_q};
+  const size_t lds = batched_lds_bytes(bl.block, bl.cap_big, bl.cap_quad, bl.cap_wave);
   hipError_t e = allow_lds(bl.block, lds);
   if (e != hipSuccess) return e;
   if (bl.block == 256) hipLaunchKernelGGL(k_batched<256>, dim3(bl.grid), dim3(256), lds, s, a);
@@ -513,9 +584,11 @@ hipError_t launch_batched(const BatchLaunch &bl, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t batched_lds_bytes(int block, int cap_big, int cap_wave) {
+size_t batched_lds_bytes(int block, int cap_big, int cap_quad, int cap_wave) {
   const size_t a = Slot::bytes(cap_big), b = (size_t)(block / 64) * Slot::bytes(cap_wave);
-  return a > b ? a : b;
+  const size_t q = block > QG ? (size_t)(block / QG) * Slot::bytes(cap_quad) : 0;
+  const size_t m = a > b ? a : b;
+  return m > q ? m : q;
 }
 
 hipError_t batched_max_grid(int block, size_t lds, int *grid) {

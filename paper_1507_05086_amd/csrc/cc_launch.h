@@ -41,7 +41,7 @@ struct BatchLaunch {
   const int32_t *order;
   int32_t *labels;
   const int32_t *queue;
-  int32_t n_big, num_graphs, cap_big, cap_wave;
+  int32_t n_big, n_quad, num_graphs, cap_big, cap_quad, cap_wave;
   unsigned *heads;
   int32_t *rounds;
   unsigned long long *stat;
@@ -51,7 +51,7 @@ struct BatchLaunch {
   int block, grid;
 };
 hipError_t launch_batched(const BatchLaunch &bl, hipStream_t s);
-size_t batched_lds_bytes(int block, int cap_big, int cap_wave);
+size_t batched_lds_bytes(int block, int cap_big, int cap_quad, int cap_wave);
 hipError_t batched_max_grid(int block, size_t lds, int *grid);
 
 // Internal renumbering of a single graph (hubs first): perm (input id ->

@@ -9,7 +9,7 @@ the policy can only change the number of rounds and the time.
 Labels (rollout from a replayed state).  A state is the loop just before
 round i of a recorded run.  It is rebuilt exactly by replaying the recorded
 batch sizes B_0..B_{i-1} through the TRACE policy; the rest of the run then
-uses the fixed rule with each candidate eps_k in {2^k / 16 : k = 0..8}, and
+uses the fixed rule with each candidate eps_k in {2^(k/2) / 16 : k = 0..16}, and
 the candidate whose whole run is fastest is the target eps* (the replayed
 prefix is the same for every candidate, so comparing whole runs compares the
 remainders).  A one-round look-ahead (most vertices clustered per microsecond
@@ -40,7 +40,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "policy_weights.json")
-CANDIDATES = [2.0 ** k / 16.0 for k in range(9)]
+CANDIDATES = [2.0 ** (k / 2.0) / 16.0 for k in range(17)]  # 1/16 .. 16 in half octaves
 EPS_MIN, EPS_MAX = 1.0 / 16.0, 16.0
 
 
@@ -231,9 +231,9 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     tr = sub.add_parser("train")
     tr.add_argument("--scales", default="18,19,20,21,22,23,24")
-    tr.add_argument("--per-run", type=int, default=16)
+    tr.add_argument("--per-run", type=int, default=24)
     tr.add_argument("--bases", default="0.5,2,8")
-    tr.add_argument("--passes", type=int, default=2)
+    tr.add_argument("--passes", type=int, default=3)
     tr.add_argument("--steps", type=int, default=4000)
     tr.add_argument("--lr", type=float, default=3e-3)
     tr.add_argument("--seed", type=int, default=7)

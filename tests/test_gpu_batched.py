@@ -83,8 +83,10 @@ def sbm(ngraphs, seed, nmax=5000):
     return graphgen.sbm_batch(sizes, blocks, 0.3, 0.01, seed)
 
 
-# (block, wave_max_n); every shape fits 160 KB of LDS for graphs up to 5000 vertices
-SHAPES = [(256, 0), (1024, 0), (256, 1500), (512, 300), (1024, 400), (256, 128)]
+# (block, wave_max_n[, quad_max_n]); every shape fits 160 KB of LDS for graphs up
+# to 5000 vertices (four 4-wave sub-groups of a 1024 workgroup hold <= ~1900 each)
+SHAPES = [(256, 0), (1024, 0), (256, 1500), (512, 300), (1024, 400), (256, 128),
+          (512, 256, 2048), (1024, 200, 1500), (512, 0, 3000), (1024, 0, 1800)]
 
 
 @pytest.fixture(scope="module")
@@ -133,7 +135,7 @@ def test_degenerate_members(cc):
     g = stack(members)
     gh = upload_batch(cc, g)
     order = graphgen.batch_permutations(g.vtx_ptr, 9)
-    for shape in ((256, 0), (1024, 100), (256, 1000)):
+    for shape in ((256, 0), (1024, 100), (256, 1000), (1024, 100, 1500), (512, 0, 3100)):
         cc.cc_batch_set_config(gh, *shape)
         for algo in (oracle.C4, oracle.CW):
             for eps in (0.5, 0.05, 20.0):
@@ -155,7 +157,7 @@ def test_largest_member(cc):
     g = stack([big, graphgen.erdos_renyi(500, 8.0, seed=5), big])
     gh = upload_batch(cc, g)
     order = graphgen.batch_permutations(g.vtx_ptr, 4)
-    for shape in ((1024, 0), (256, 600)):
+    for shape in ((1024, 0), (256, 600), (512, 400, 600)):
         cc.cc_batch_set_config(gh, *shape)
         for algo in (oracle.C4, oracle.CW):
             check_batch(cc, algo, g, gh, order, 0.5)
@@ -167,7 +169,7 @@ def test_autotune_then_run(cc):
     order = graphgen.batch_permutations(g.vtx_ptr, 17)
     torch = torch_cuda()
     best = cc.cc_batch_autotune(gh, torch.from_numpy(order).cuda(), cc.CC_ALGO_C4, 0.5)
-    assert best.block in (256, 512, 1024) and best.wave_max_n >= 0 and best.ms > 0
+    assert best.block in (256, 512, 1024) and best.wave_max_n >= 0 and best.quad_max_n >= 0 and best.ms > 0
     check_batch(cc, oracle.C4, g, gh, order, 0.5)
     # a new handle of the same size class picks the tuned shape up
     gh2 = upload_batch(cc, g)
