@@ -149,7 +149,7 @@ def bench_batched(cc, torch, steps):
         wall = (time.perf_counter() - t0) / steps
         out[name] = {"launch_ms": round(float(np.median(ks)), 3), "call_ms": round(wall * 1e3, 3),
                      "edges_per_s": g.m / (float(np.median(ks)) / 1e3), "max_rounds": st.rounds,
-                     "shape": {"block": best.block, "wave_max_n": best.wave_max_n}, "autotune_s": round(tune_s, 2)}
+                     "shape": {"block": best.block, "wave_max_n": best.wave_max_n, "quad_max_n": best.quad_max_n}, "autotune_s": round(tune_s, 2)}
     # ablation: the same graphs one call each (every 16th graph, scaled by 16)
     sample = list(range(0, g.ngraphs, 16))
     handles = []
