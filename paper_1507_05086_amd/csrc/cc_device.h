@@ -94,6 +94,9 @@ struct Ctrl {
   // per-round statistics spread over 64 slots (slot = workgroup mod 64): one
   // address taken by every workgroup would serialise their atomics
   unsigned long long spread_atom[64], spread_conf[64];
+  // active vertices of this round settled by the selection itself (no
+  // unclustered neighbour: a center that claims nobody), spread the same way
+  unsigned long long spread_lone[64];
 };
 
 // A listed vertex's row: start of its adjacency in col, its degree and its

@@ -416,6 +416,7 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
   __shared__ int64_t sh[SEL_BS / 64 + 1];
   __shared__ unsigned long long s_base;
   const long long B = c->b, cur0 = c->cursor;
+  const bool exact = c->phase == PHASE_EXACT;
   const int64_t n = w.n;
   // Workgroups this round can use: B_i unclustered are spread over the
   // positions ahead with density n_i / (n - cursor); extra groups would only
@@ -463,9 +464,12 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     }
     __syncthreads();
     const long long excl = s_excl;
-    // the first (B - excl) unclustered positions of this tile are active
+    // the first (B - excl) unclustered positions of this tile are active.  An
+    // active vertex with no unclustered neighbour (degree 0, or an exact
+    // remaining degree of 0) is a center that claims nobody and that no
+    // other active vertex can see: it is settled here and never listed.
     int64_t wsum = 0;
-    int cnt = 0;
+    int cnt = 0, lone = 0;
     unsigned act = 0;
     int32_t wt[SIPT];
     int64_t rs[SIPT];
@@ -476,11 +480,18 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
       rs[k] = 0;
       if (un & (1u << k)) {
         if (r < B) {
-          act |= 1u << k;
-          cnt++;
-          rs[k] = w.off[vv[k]];
-          wt[k] = (int32_t)(w.off[vv[k] + 1] - rs[k]);  // degree here; weight max(deg, 1) below
-          wsum += wt[k] > 0 ? wt[k] : 1;
+          const int32_t v = vv[k];
+          rs[k] = w.off[v];
+          wt[k] = (int32_t)(w.off[v + 1] - rs[k]);
+          if (wt[k] == 0 || (exact && w.ub[v] == 0)) {
+            w.lab[v] = (int32_t)(base + k);
+            atomicAnd(&w.unc[v >> 5], ~(1u << (v & 31)));
+            lone++;
+          } else {
+            act |= 1u << k;
+            cnt++;
+            wsum += wt[k];
+          }
           if (r == B - 1) {
             c->r_last = base + k;
             st_rel(&c->select_done, 1);
@@ -491,8 +502,12 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     }
     int64_t wtot, ctot;
     const int64_t wpre = wg_excl_scan<SEL_BS>(wsum, &wtot, sh);
-    const int64_t cpre = wg_excl_scan<SEL_BS>(cnt, &ctot, sh);
+    // listed count in the low 32 bits, settled count above (a tile holds < 2^32)
+    const int64_t cpre = wg_excl_scan<SEL_BS>((int64_t)cnt | ((int64_t)lone << 32), &ctot, sh) & 0xFFFFFFFFll;
+    const int64_t ltot = ctot >> 32;
+    ctot &= 0xFFFFFFFFll;
     if (threadIdx.x == 0 && ctot > 0) s_base = atomicAdd(&c->a_pack, pk(wtot, ctot));
+    if (threadIdx.x == 0 && ltot > 0) atomicAdd(&c->spread_lone[blockIdx.x & 63], (unsigned long long)ltot);
     __syncthreads();
     if (ctot > 0) {
       int64_t slot = pk_cnt(s_base) + cpre, wpos = pk_work(s_base) + wpre;
@@ -506,7 +521,7 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
           w.awork[slot] = wpos;
           w.ainfo[slot] = RowInfo{rs[k], wt[k], (int32_t)(base + k)};
           slot++;
-          wpos += wt[k] > 0 ? wt[k] : 1;
+          wpos += wt[k];
         }
       }
     }
@@ -842,12 +857,15 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
   const long long now = (long long)wall_clock64();
+  long long lone = 0;  // centers settled by k_select
   {  // fold the spread statistics of the round
     const int l = lane_id();
     const unsigned long long sa = (unsigned long long)wave_sum((int64_t)c->spread_atom[l]);
     const unsigned long long sc = (unsigned long long)wave_sum((int64_t)c->spread_conf[l]);
+    lone = wave_sum((int64_t)c->spread_lone[l]);
     c->spread_atom[l] = 0;
     c->spread_conf[l] = 0;
+    c->spread_lone[l] = 0;
     if (l == 0) {
       c->sum_atomics += sa;
       c->conflicts += sc;
@@ -862,8 +880,8 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
     if (c->has_round) {
       const int phase_run = c->phase;  // phase the finished round ran in
       const bool c4 = w.algo == ALGO_C4;
-      const long long centers = c4 ? pk_cnt(c->c_pack) : pk_cnt(c->a_pack);
-      const long long newly = pk_cnt(c->n_pack);
+      const long long centers = (c4 ? pk_cnt(c->c_pack) : pk_cnt(c->a_pack)) + lone;
+      const long long newly = pk_cnt(c->n_pack) + lone;
       const long long conf = c4 ? (long long)c->n_blocked : (long long)c->conflicts;
       if (c->round < w.trace_cap) {
         RoundRec r;
