@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -86,6 +87,8 @@ struct Workspace {
   int64_t sched_cap = 0;
   float *mlp = nullptr;
   int *host_flags = nullptr;  // pinned: done, error, has_round, fallback, phase
+  unsigned long long *progress = nullptr;  // pinned, coherent: k_close's progress word
+  unsigned long long *progress_dev = nullptr;  // the same word as the device addresses it
   int32_t *cost_size = nullptr;
   long long *cost_acc = nullptr;
   int *dev_err = nullptr;
@@ -148,6 +151,7 @@ void free_ws(Workspace &w) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (w.host_flags) (void)hipHostFree(w.host_flags);
+  if (w.progress) (void)hipHostFree(w.progress);
   for (RoundGraph &g : w.graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (w.cap) (void)hipStreamDestroy(w.cap);
@@ -227,6 +231,8 @@ int32_t ensure_ws(cc_graph *g) {
   HIP_TRY(dalloc(&w.cost_acc, 2 * (size_t)g->num_graphs));
   HIP_TRY(dalloc(&w.dev_err, 1));
   HIP_TRY(hipHostMalloc((void **)&w.host_flags, 8 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void **)&w.progress, sizeof(unsigned long long), hipHostMallocCoherent | hipHostMallocMapped));
+  HIP_TRY(hipHostGetDevicePointer((void **)&w.progress_dev, w.progress, 0));
   w.ready = true;
   return CC_OK;
 }
@@ -241,6 +247,10 @@ int32_t wall_clock_khz(int *khz) {
 
 int32_t run_batch(cc_graph *g, int algo, const int32_t *order, double eps, int32_t *labels, cc_run_stats *stats,
                   uint32_t flags, hipStream_t s);
+
+// Rounds per queued group.  Small enough that a finished run leaves little
+// behind it, large enough that the host stays ahead of the device.
+constexpr int64_t kRoundGroup = 4;
 
 // Queues k rounds on s as one graph launch: the round's kernels are captured
 // once per (arguments, phase, k) and replayed; the host then issues one call
@@ -378,8 +388,10 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.eps_min = (float)pol.eps_min;
   w.eps_max = (float)pol.eps_max;
   w.max_rounds = stats ? stats->max_rounds : 0;
+  w.progress = ws.progress_dev;
 
   // init: the permutation is checked before any kernel indexes with it
+  __atomic_store_n(ws.progress, 0ull, __ATOMIC_RELEASE);  // nothing of this handle is in flight
   HIP_TRY(hipMemsetAsync(ws.ctrl, 0, sizeof(Ctrl), s));
   HIP_TRY(hipMemsetAsync(ws.rank, 0xFF, sizeof(int32_t) * (size_t)n, s));
   HIP_TRY(hipMemsetAsync(ws.hist, 0, sizeof(int) * (size_t)ws.hist_len, s));
@@ -393,7 +405,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   if (ws.host_flags[1]) return fail(CC_ERR_DEVICE, "device error during initialisation");
 
   LaunchShape ls{256, 1024, 512, 0, 0};
-  int64_t launched = 0, group = 4;
+  int64_t launched = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   HIP_TRY(hipEventCreate(&ev0));
   HIP_TRY(hipEventCreate(&ev1));
@@ -405,31 +417,52 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     }
   } evg{ev0, ev1};
   HIP_TRY(hipEventRecord(ev0, s));
+  // Two groups of rounds stay queued: while one runs, the host waits on the
+  // progress word for the older one and queues the next.  The device never
+  // idles on the host, and a finished run leaves at most one group and the
+  // rest of the current one (all kernels return at once) behind it.
+  if (int32_t rc = launch_rounds(ws, w, ls, kRoundGroup, s)) return rc;
+  launched = kRoundGroup;
   for (;;) {
-    if (int32_t rc = launch_rounds(ws, w, ls, group, s)) return rc;
-    launched += group;
-    HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->done, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (ws.host_flags[0] || ws.host_flags[1]) break;
-    if (ws.host_flags[4] == PHASE_EXACT) ls.exact_seen = 1;
+    const int64_t older = launched;
+    if (int32_t rc = launch_rounds(ws, w, ls, kRoundGroup, s)) return rc;
+    launched += kRoundGroup;
+    bool done = false;
+    for (unsigned spin = 1;; spin++) {
+      const unsigned long long p = __atomic_load_n(ws.progress, __ATOMIC_ACQUIRE);
+      done = (p >> PROGRESS_DONE & 1) || (p >> PROGRESS_ERROR & 1);
+      if (p >> PROGRESS_EXACT & 1) ls.exact_seen = 1;
+      if (done || (int64_t)(p & 0xFFFFFFFFull) >= older) break;
+      if (spin % 64 == 0) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q != hipErrorNotReady) {  // drained: read the state itself
+          HIP_TRY(q);
+          HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->done, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+          HIP_TRY(hipStreamSynchronize(s));
+          done = ws.host_flags[0] || ws.host_flags[1];
+          if (ws.host_flags[4] == PHASE_EXACT) ls.exact_seen = 1;
+          break;
+        }
+      }
+      std::this_thread::yield();
+    }
+    if (done) break;
     if (launched > n + 2) return fail(CC_ERR_NO_PROGRESS, "round loop exceeded n+1 rounds");
-    // while the lazy degree search runs, look at the phase every 32 rounds:
-    // its extra kernels stay queued until the host sees the switch
-    group = group * 2 < (ls.exact_seen ? 64 : 32) ? group * 2 : (ls.exact_seen ? 64 : 32);
   }
   HIP_TRY(hipEventRecord(ev1, s));
-  if (ws.host_flags[1]) {
-    const int e = ws.host_flags[1];
+  Ctrl hc;
+  HIP_TRY(hipMemcpyAsync(&hc, ws.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  int32_t *d_labels = (flags & CC_OUTPUT_ON_DEVICE) ? labels : ws.label_buf;
+  HIP_TRY(launch_finalize(w, d_labels, s));
+  HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hc.error) {  // the finalize pass above wrote nothing the caller may use
+    const int e = hc.error;
     if (e == ERR_NO_PROGRESS) return fail(CC_ERR_NO_PROGRESS, "round loop made no progress");
     if (e == ERR_OVERFLOW) return fail(CC_ERR_DEVICE, "a device work list overflowed");
     return fail(CC_ERR_DEVICE, "device error " + std::to_string(e) + " in the round loop");
   }
-  int32_t *d_labels = (flags & CC_OUTPUT_ON_DEVICE) ? labels : ws.label_buf;
-  HIP_TRY(launch_finalize(w, d_labels, s));
-  Ctrl hc;
-  HIP_TRY(hipMemcpyAsync(&hc, ws.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (hc.error) return fail(CC_ERR_DEVICE, "device error " + std::to_string(hc.error) + " while finishing");
+  if (ws.host_flags[0]) return fail(CC_ERR_DEVICE, "device error " + std::to_string(ws.host_flags[0]) + " while finishing");
   if (!(flags & CC_OUTPUT_ON_DEVICE)) {
     HIP_TRY(hipMemcpyAsync(labels, ws.label_buf, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

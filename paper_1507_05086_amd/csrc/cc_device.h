@@ -151,7 +151,13 @@ struct Ws {
   const float *mlp;     // LEARNED: 6-64-1 weights (device)
   float eps_min, eps_max;
   int64_t max_rounds;   // > 0: stop after this many rounds (partial run)
+  // progress word in pinned host memory, written by k_close at the end of
+  // every round: rounds finished (bits 0..31), done (32), exact phase (33),
+  // error (34)
+  unsigned long long *progress;
 };
+
+constexpr int PROGRESS_DONE = 32, PROGRESS_EXACT = 33, PROGRESS_ERROR = 34;
 
 __host__ __device__ inline int level_of(int64_t x) {  // floor(log2(x)), x >= 1
   int l = 0;

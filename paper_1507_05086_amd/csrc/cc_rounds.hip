@@ -985,6 +985,12 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
       c->t_start = now;
     }
   }
+  if (threadIdx.x == 0 && w.progress) {
+    const unsigned long long p = (unsigned long long)(unsigned)round | (unsigned long long)(done != 0) << PROGRESS_DONE |
+                                 (unsigned long long)(c->phase == PHASE_EXACT) << PROGRESS_EXACT |
+                                 (unsigned long long)(c->error != 0) << PROGRESS_ERROR;
+    __hip_atomic_store(w.progress, p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // ----------------------------------------------------------- finalize -----
