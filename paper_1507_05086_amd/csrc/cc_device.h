@@ -114,6 +114,7 @@ struct Ws {
   const int32_t *col;
   int64_t n;
   int64_t max_deg;
+  int64_t iso_start;        // internal ids from here on have degree 0 (they sort last)
   // run input
   const int32_t *order;     // pi in internal ids (written by k_invert)
   int32_t *iorder;          // the same buffer, writable

@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
   unsigned long long *xacc = (unsigned long long *)w.awork;
   __shared__ StageBuf<2 * BS> sb;
   stage_init(sb);
-  const int64_t n = w.n;
+  const int64_t n = w.iso_start;  // the isolated vertices after it have no row
   const int64_t per = ((n + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
   const int64_t v0 = (int64_t)blockIdx.x * per, v1 = v0 + per < n ? v0 + per : n;
   for (int64_t vb = v0; vb < v1; vb += BS) {
@@ -444,10 +444,12 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
       const int64_t p = base + k;
       vv[k] = p < n ? w.order[p] : 0;
     }
+    // an isolated vertex's bit is never cleared: only its own position,
+    // which the cursor passes once, asks whether it is clustered
 #pragma unroll
     for (int k = 0; k < SIPT; k++) {
       const int64_t p = base + k;
-      if (p < n && unc_bit(w.unc, vv[k])) un |= 1u << k;
+      if (p < n && (vv[k] >= w.iso_start || unc_bit(w.unc, vv[k]))) un |= 1u << k;
     }
     int64_t agg;
     const int64_t mine = wg_excl_scan<SEL_BS>(__popc(un), &agg, sh);
@@ -467,9 +469,12 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     // the first (B - excl) unclustered positions of this tile are active.  An
     // active vertex with no unclustered neighbour (degree 0, or an exact
     // remaining degree of 0) is a center that claims nobody and that no
-    // other active vertex can see: it is settled here and never listed.
+    // other active vertex can see: it is settled here and never listed.  Its
+    // label stays unset; k_finalize recognises it (isolated and passed by the
+    // cursor, or its bit cleared with no label) and makes it its own center.
     int64_t wsum = 0;
     int cnt = 0, lone = 0;
+    unsigned clears = 0;
     unsigned act = 0;
     int32_t wt[SIPT];
     int64_t rs[SIPT];
@@ -481,13 +486,15 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
       if (un & (1u << k)) {
         if (r < B) {
           const int32_t v = vv[k];
-          rs[k] = w.off[v];
-          wt[k] = (int32_t)(w.off[v + 1] - rs[k]);
-          if (wt[k] == 0 || (exact && w.ub[v] == 0)) {
-            w.lab[v] = (int32_t)(base + k);
+          if (v >= w.iso_start) {
+            lone++;
+          } else if (exact && w.ub[v] == 0) {
             atomicAnd(&w.unc[v >> 5], ~(1u << (v & 31)));
             lone++;
+            clears++;
           } else {
+            rs[k] = w.off[v];
+            wt[k] = (int32_t)(w.off[v + 1] - rs[k]);
             act |= 1u << k;
             cnt++;
             wsum += wt[k];
@@ -508,6 +515,10 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     ctot &= 0xFFFFFFFFll;
     if (threadIdx.x == 0 && ctot > 0) s_base = atomicAdd(&c->a_pack, pk(wtot, ctot));
     if (threadIdx.x == 0 && ltot > 0) atomicAdd(&c->spread_lone[blockIdx.x & 63], (unsigned long long)ltot);
+    if (clears) {
+      const int64_t wc = wave_sum((int64_t)clears);
+      if (lane_id() == 0) atomicAdd(&c->spread_atom[blockIdx.x & 63], (unsigned long long)wc);
+    }
     __syncthreads();
     if (ctot > 0) {
       int64_t slot = pk_cnt(s_base) + cpre, wpos = pk_work(s_base) + wpre;
@@ -902,7 +913,7 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
       c->sum_claim += c4 ? (unsigned long long)pk_work(c->c_pack) : (unsigned long long)pk_work(c->a_pack);
       c->sum_rescan += resc;
       c->sum_peel += phase_run == PHASE_EXACT ? (unsigned long long)pk_work(c->p_pack) : 0ull;
-      c->sum_atomics += (unsigned long long)newly;  // bitmap clears
+      c->sum_atomics += (unsigned long long)pk_cnt(c->n_pack);  // bitmap clears of the listed
       c->sum_blocked += (unsigned long long)conf;
       c->feat_conf = c->b > 0 ? (float)conf / (float)c->b : 0.f;
       c->feat_claim = c->n_start > 0 ? (float)(newly - centers) / (float)c->n_start : 0.f;
@@ -997,11 +1008,17 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
 
 __global__ void __launch_bounds__(BS) k_finalize(Ws w, int32_t *labels) {
   const int64_t n = w.n;
+  const long long cursor = w.ctrl->cursor;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
     // labels are indexed and valued in input ids
     const int32_t l = w.lab[v];
     const int32_t vin = w.iperm[v];
-    if (l == INF && w.max_rounds > 0) {
+    // no label: a center k_select settled (an isolated vertex the cursor
+    // passed, or a vertex whose bit it cleared), or still unclustered
+    const bool lone = l == INF && (v >= w.iso_start ? (long long)w.rank[v] < cursor : !unc_bit(w.unc, (int32_t)v));
+    if (lone) {
+      labels[vin] = vin;
+    } else if (l == INF && w.max_rounds > 0) {
       labels[vin] = -1;  // a partial run left v unclustered
     } else if (l < 0 || (int64_t)l >= n) {
       set_error(w.ctrl, ERR_LABEL);
