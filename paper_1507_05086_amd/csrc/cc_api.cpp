@@ -129,7 +129,8 @@ struct cc_graph {
   int32_t *perm = nullptr, *iperm = nullptr, *rcol = nullptr;
   int64_t *roff = nullptr;
   int64_t max_deg = 0;
-  int64_t iso_start = 0;       // single graphs: internal ids >= iso_start have degree 0
+  int64_t low_start = 0;       // single graphs: internal ids >= low_start have degree < DSW,
+  int64_t iso_start = 0;       // and those >= iso_start degree 0
   int64_t n_hi = 0;            // vertices with degree >= DSW
   int32_t *lvl_init = nullptr; // device: initial bound buckets
   int64_t *lvl_off = nullptr;  // device [NLVL+1]
@@ -346,6 +347,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.perm = g->perm;
   w.iperm = g->iperm;
   w.max_deg = g->max_deg;
+  w.low_start = g->low_start;
   w.iso_start = g->iso_start;
   w.rank = ws.rank;
   w.lab = ws.lab;
@@ -914,7 +916,7 @@ int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_
     if (re == hipSuccess) re = dalloc(&bsum, (size_t)(n_total / (4 * BS) + 4));
     if (re == hipSuccess)
       re = launch_relabel(g->off, g->col, g->wall, n_total, cnt, binoff, g->perm, g->iperm, rdeg, g->roff, bsum,
-                          g->rcol, &g->iso_start, s);
+                          g->rcol, &g->low_start, &g->iso_start, s);
     if (re == hipSuccess) re = hipStreamSynchronize(s);
     void *tmp[] = {cnt, binoff, rdeg, bsum};
     for (void *p : tmp)

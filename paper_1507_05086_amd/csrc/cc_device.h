@@ -86,7 +86,8 @@ struct Ctrl {
   unsigned long long r_pack[DITER];
   int d_max[DITER];
   int pad2;
-  unsigned long long x_pack;  // rows recounted when switching to exact degrees
+  unsigned long long x_pack;  // rows of degree >= DSW recounted when switching to exact degrees
+  unsigned long long x_low[64];  // adjacency entries of the lower-degree rows recounted then (spread)
   // bound buckets: entries per level (capacity fixed per graph)
   unsigned int lvl_cnt[NLVL];
   // run totals
@@ -114,7 +115,8 @@ struct Ws {
   const int32_t *col;
   int64_t n;
   int64_t max_deg;
-  int64_t iso_start;        // internal ids from here on have degree 0 (they sort last)
+  int64_t low_start;        // internal ids from here on have degree < DSW ...
+  int64_t iso_start;        // ... and from here on degree 0 (they sort last)
   // run input
   const int32_t *order;     // pi in internal ids (written by k_invert)
   int32_t *iorder;          // the same buffer, writable

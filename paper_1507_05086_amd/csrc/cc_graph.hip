@@ -308,7 +308,9 @@ __global__ void __launch_bounds__(BS) k_relabel_cols(const int64_t *off, const i
 
 hipError_t launch_relabel(const int64_t *off, const int32_t *col, const int64_t *wall, int64_t n, unsigned *count,
                           int64_t *bin_off_dev, int32_t *perm, int32_t *iperm, int64_t *rdeg, int64_t *roff,
-                          int64_t *blocksum, int32_t *rcol, int64_t *first_isolated, hipStream_t s) {
+                          int64_t *blocksum, int32_t *rcol, int64_t *first_low, int64_t *first_isolated,
+                          hipStream_t s) {
+  *first_low = n;
   *first_isolated = n;
   if (n == 0) return hipMemsetAsync(roff, 0, sizeof(int64_t), s);
   const unsigned g = (unsigned)((n + BS - 1) / BS < 4096 ? (n + BS - 1) / BS : 4096);
@@ -325,6 +327,7 @@ hipError_t launch_relabel(const int64_t *off, const int32_t *col, const int64_t 
     acc += hc[b];
   }
   *first_isolated = hb[RBINS - 1];
+  *first_low = hb[NLVL - 1 - level_of(DSW - 1)];  // the bin of degree DSW - 1
   e = hipMemcpyAsync(bin_off_dev, hb, sizeof(hb), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_relabel_assign, dim3(g), dim3(BS), 0, s, off, n, bin_off_dev, count + RBINS, perm, iperm);

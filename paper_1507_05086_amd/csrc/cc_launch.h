@@ -57,11 +57,13 @@ hipError_t batched_max_grid(int block, size_t lds, int *grid);
 // Internal renumbering of a single graph (hubs first): perm (input id ->
 // internal id), iperm, and the renumbered CSR roff / rcol.  count: 2 x
 // (NLVL + 1) unsigned scratch, bin_off: NLVL + 1 int64, rdeg: n int64,
-// blocksum: n / (4 BS) + 2 int64.  *first_isolated (host) = the first
-// internal id of degree 0: the isolated vertices are the ids from there on.
+// blocksum: n / (4 BS) + 2 int64.  On the host: *first_low = the first
+// internal id of degree below DSW, *first_isolated = the first of degree 0
+// (degrees fall with the id level by level, so each is the start of a range).
 hipError_t launch_relabel(const int64_t *off, const int32_t *col, const int64_t *wall, int64_t n, unsigned *count,
                           int64_t *bin_off_dev, int32_t *perm, int32_t *iperm, int64_t *rdeg, int64_t *roff,
-                          int64_t *blocksum, int32_t *rcol, int64_t *first_isolated, hipStream_t s);
+                          int64_t *blocksum, int32_t *rcol, int64_t *first_low, int64_t *first_isolated,
+                          hipStream_t s);
 
 // Learned-policy network: inference over a batch, one training step.
 int mlp_grad_blocks(int n);

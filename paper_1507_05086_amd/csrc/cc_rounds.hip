@@ -309,8 +309,9 @@ __global__ void __launch_bounds__(BS) k_rescan(Ws w) {
   if (threadIdx.x == 0 && s_max > 0) atomicMax(&c->d_max[IT], s_max);
 }
 
-// Switch to exact degrees: list the unclustered rows (their accumulators
-// live in the active-list weights, free at this point of the round) ...
+// Switch to exact degrees: list the unclustered rows of degree >= DSW (their
+// accumulators live in the active-list weights, free at this point of the
+// round) ...
 __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
@@ -319,7 +320,7 @@ __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
   unsigned long long *xacc = (unsigned long long *)w.awork;
   __shared__ StageBuf<2 * BS> sb;
   stage_init(sb);
-  const int64_t n = w.iso_start;  // the isolated vertices after it have no row
+  const int64_t n = w.low_start;  // lower-degree rows are counted by id in k_xcount
   const int64_t per = ((n + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
   const int64_t v0 = (int64_t)blockIdx.x * per, v1 = v0 + per < n ? v0 + per : n;
   for (int64_t vb = v0; vb < v1; vb += BS) {
@@ -334,7 +335,10 @@ __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
   stage_flush(sb, &c->x_pack, w.xlist, w.xwork, xacc);
 }
 
-// ... and count their unclustered neighbours into ub and the histogram.
+// ... and count their unclustered neighbours into ub and the histogram: the
+// listed rows edge-balanced, the rows of degree below DSW (ids low_start ..
+// iso_start, by falling level) one lane per row, so a wave's rows are of
+// about one length and no search or barrier is needed.
 __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
@@ -365,6 +369,28 @@ __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
         int total = cj;
         if (covered == deg || row_combine(xacc, slot, cj, covered, deg, &total)) finalize(v, total);
       });
+  static_assert(DSW <= HLDS, "a lower-degree row's count fits the LDS histogram");
+  int64_t scanned = 0;
+  for (int64_t v = w.low_start + (int64_t)blockIdx.x * BS + threadIdx.x; v < w.iso_start;
+       v += (int64_t)gridDim.x * BS) {
+    if (!unc_bit(w.unc, (int32_t)v)) continue;
+    const int64_t s0 = w.off[v];
+    const int d = (int)(w.off[v + 1] - s0);
+    int r = 0;
+    for (int j = 0; j < d; j += 4) {
+      int32_t u[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) u[q] = j + q < d ? w.col[s0 + j + q] : -1;
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (u[q] >= 0 && unc_bit(w.unc, u[q])) r++;
+    }
+    scanned += d;
+    w.ub[v] = r;
+    if (r > 0) atomicAdd(&s_hist[r], 1);
+  }
+  const int64_t wsc = wave_sum(scanned);
+  if (lane_id() == 0 && wsc) atomicAdd(&c->x_low[(blockIdx.x * (BS / 64) + wave_id()) & 63], (unsigned long long)wsc);
   __syncthreads();
   for (int i = threadIdx.x; i < HLDS; i += BS)
     if (s_hist[i]) atomicAdd(&w.hist[i], s_hist[i]);
@@ -869,14 +895,17 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
   if (c->done) return;
   const long long now = (long long)wall_clock64();
   long long lone = 0;  // centers settled by k_select
+  long long xlow = 0;  // entries of lower-degree rows recounted at the switch
   {  // fold the spread statistics of the round
     const int l = lane_id();
     const unsigned long long sa = (unsigned long long)wave_sum((int64_t)c->spread_atom[l]);
     const unsigned long long sc = (unsigned long long)wave_sum((int64_t)c->spread_conf[l]);
     lone = wave_sum((int64_t)c->spread_lone[l]);
+    xlow = wave_sum((int64_t)c->x_low[l]);
     c->spread_atom[l] = 0;
     c->spread_conf[l] = 0;
     c->spread_lone[l] = 0;
+    c->x_low[l] = 0;
     if (l == 0) {
       c->sum_atomics += sa;
       c->conflicts += sc;
@@ -907,7 +936,7 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
         r.t_ns = now - c->t_start;
         w.trace[c->round] = r;
       }
-      unsigned long long resc = pk_work(c->x_pack);
+      unsigned long long resc = pk_work(c->x_pack) + (unsigned long long)xlow;
       for (int j = 0; j < DITER; j++) resc += pk_work(c->r_pack[j]);
       c->sum_elect += c4 ? (unsigned long long)pk_work(c->a_pack) : 0ull;
       c->sum_claim += c4 ? (unsigned long long)pk_work(c->c_pack) : (unsigned long long)pk_work(c->a_pack);
