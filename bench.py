@@ -69,7 +69,7 @@ def measured_traffic(workload):
     return d
 
 
-CALL_FIRST, CALL_LAST = "k_invert", "k_finalize"
+CALL_FIRST, CALL_LAST = "k_check_order", "k_finalize"
 
 
 def summarize_counters(fetch_csv, write_csv, workload, copy_mb):

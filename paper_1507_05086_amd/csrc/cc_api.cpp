@@ -148,8 +148,7 @@ void free_ws(Workspace &w) {
   void *ptrs[] = {w.rank, w.lab, w.ub, w.unc, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
                   w.awork, w.cwork, w.nwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist, w.plist, w.pwork,
                   w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf, w.label_buf, w.sched, w.mlp, w.ainfo, w.cinfo,
-                  w.iorder,
-                  w.cost_size, w.cost_acc, w.dev_err};
+                  w.iorder, w.cost_size, w.cost_acc, w.dev_err};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (w.host_flags) (void)hipHostFree(w.host_flags);
@@ -397,7 +396,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   // init: the permutation is checked before any kernel indexes with it
   __atomic_store_n(ws.progress, 0ull, __ATOMIC_RELEASE);  // nothing of this handle is in flight
   HIP_TRY(hipMemsetAsync(ws.ctrl, 0, sizeof(Ctrl), s));
-  HIP_TRY(hipMemsetAsync(ws.rank, 0xFF, sizeof(int32_t) * (size_t)n, s));
+  HIP_TRY(hipMemsetAsync(ws.state, 0, (size_t)n, s));  // k_check_order marks the vertices pi names
   HIP_TRY(hipMemsetAsync(ws.hist, 0, sizeof(int) * (size_t)ws.hist_len, s));
   if (g->lvl_total > 0)
     HIP_TRY(hipMemcpyAsync(ws.lvl, g->lvl_init, sizeof(int32_t) * (size_t)g->lvl_total, hipMemcpyDeviceToDevice, s));
@@ -408,7 +407,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     return fail(CC_ERR_NOT_PERMUTATION, "order is not a permutation of 0..n-1");
   if (ws.host_flags[1]) return fail(CC_ERR_DEVICE, "device error during initialisation");
 
-  LaunchShape ls{256, 1024, 512, 0, 0};
+  LaunchShape ls{512, 1024, 512, 0, 0};
   int64_t launched = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   HIP_TRY(hipEventCreate(&ev0));

@@ -29,7 +29,7 @@ constexpr int SEL_BS = 256;         // threads of an active-set scan workgroup
 constexpr int TSEL = SEL_BS * SIPT; // pi positions per scan tile
 constexpr int32_t INF = 0x7fffffff;
 
-enum : uint8_t { UNCL = 0, ACTIVE = 1, CENTER = 2, NONCENTER = 3 };
+enum : uint8_t { UNCL = 0, ACTIVE = 1, CENTER = 2, NONCENTER = 3, ORDER_SEEN = 4 };
 constexpr int DSW = 64;            // bounds below this never need a bucket entry
 constexpr int LVL_MIN = 6;         // log2(DSW): lowest bucket level of the bound buckets
 constexpr int NLVL = 32;           // bucket levels (level = floor(log2(ub)))
@@ -118,7 +118,7 @@ struct Ws {
   int64_t low_start;        // internal ids from here on have degree < DSW ...
   int64_t iso_start;        // ... and from here on degree 0 (they sort last)
   // run input
-  const int32_t *order;     // pi in internal ids (written by k_invert)
+  const int32_t *order;     // pi in internal ids (written by k_check_order)
   int32_t *iorder;          // the same buffer, writable
   const int32_t *order_in;  // the caller's pi (input ids)
   const int32_t *perm;      // input id -> internal id

@@ -46,9 +46,13 @@ __device__ inline bool row_combine(unsigned long long *acc, int64_t slot, int cn
 
 // ------------------------------------------------------------------ init --
 
-// pi moves to internal ids and rank = pi^-1 by a plain scatter; k_init then
-// finds a missing (hence also a repeated) vertex as one left without a rank.
-__global__ void __launch_bounds__(BS) k_invert(Ws w) {
+// pi moves to internal ids (one gather, written in pi order) and must be a
+// permutation: n entries, each in range and none repeated.  Each entry marks
+// its vertex in the (zeroed) state bytes with a plain store; n entries in
+// range mark all n vertices exactly when none repeats, which k_init checks.
+// pi is not inverted: the rank of a vertex is recorded when it becomes
+// active, the only time anyone asks for it.
+__global__ void __launch_bounds__(BS) k_check_order(Ws w) {
   const int64_t n = w.n;
   for (int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x; k < n; k += (int64_t)gridDim.x * BS) {
     const int32_t v = w.order_in[k];
@@ -58,7 +62,7 @@ __global__ void __launch_bounds__(BS) k_invert(Ws w) {
     } else {
       const int32_t vi = w.perm[v];
       w.iorder[k] = vi;
-      w.rank[vi] = (int32_t)k;
+      w.state[vi] = ORDER_SEEN;
     }
   }
 }
@@ -66,9 +70,7 @@ __global__ void __launch_bounds__(BS) k_invert(Ws w) {
 __global__ void __launch_bounds__(BS) k_init(Ws w, const unsigned *lvl_init_cnt) {
   const int64_t n = w.n;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
-    // k_invert range-checked every entry of order; if every vertex also got
-    // a rank, the n entries hit n distinct vertices: order is a permutation
-    if (w.rank[v] < 0) set_error(w.ctrl, ERR_PERM);
+    if (w.state[v] != ORDER_SEEN) set_error(w.ctrl, ERR_PERM);  // no entry of pi names v
     w.lab[v] = INF;
     w.state[v] = UNCL;
     w.flag[v] = 0;
@@ -513,6 +515,7 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
         if (r < B) {
           const int32_t v = vv[k];
           if (v >= w.iso_start) {
+            if (w.max_rounds > 0) w.lab[v] = (int32_t)(base + k);  // a partial run must tell it apart
             lone++;
           } else if (exact && w.ub[v] == 0) {
             atomicAnd(&w.unc[v >> 5], ~(1u << (v & 31)));
@@ -553,7 +556,10 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
         if (act & (1u << k)) {
           const int32_t v = vv[k];
           w.state[v] = ACTIVE;
-          if (w.algo == ALGO_CW) w.lab[v] = (int32_t)(base + k);  // every active vertex is a center
+          // the rank of an active vertex, as its neighbours will ask for it:
+          // ClusterWild! keeps it as the label (every active vertex is a center)
+          if (w.algo == ALGO_CW) w.lab[v] = (int32_t)(base + k);
+          else w.rank[v] = (int32_t)(base + k);
           w.alist[slot] = v;
           w.awork[slot] = wpos;
           w.ainfo[slot] = RowInfo{rs[k], wt[k], (int32_t)(base + k)};
@@ -765,7 +771,7 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
           elig[k] = un[k];
           if (!c4 && un[k] && w.state[it.u[k]] == ACTIVE) {  // ClusterWild! claims Gamma(c) \ A
             elig[k] = false;
-            if (w.rank[it.u[k]] < it.val[k]) w.flag[it.v[k]] = 1;  // rule 1 broken
+            if (w.lab[it.u[k]] < it.val[k]) w.flag[it.v[k]] = 1;  // rule 1 broken (lab = rank here)
           }
           cur[k] = elig[k] ? w.lab[it.u[k]] : 0;  // stale reads are safe: labels only decrease
         }
@@ -1037,14 +1043,14 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
 
 __global__ void __launch_bounds__(BS) k_finalize(Ws w, int32_t *labels) {
   const int64_t n = w.n;
-  const long long cursor = w.ctrl->cursor;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
     // labels are indexed and valued in input ids
     const int32_t l = w.lab[v];
     const int32_t vin = w.iperm[v];
-    // no label: a center k_select settled (an isolated vertex the cursor
-    // passed, or a vertex whose bit it cleared), or still unclustered
-    const bool lone = l == INF && (v >= w.iso_start ? (long long)w.rank[v] < cursor : !unc_bit(w.unc, (int32_t)v));
+    // no label: a center k_select settled (an isolated vertex -- all of them
+    // once a run is complete; a partial run labels those it reached -- or a
+    // vertex whose bit it cleared), or still unclustered
+    const bool lone = l == INF && (v >= w.iso_start ? w.max_rounds == 0 : !unc_bit(w.unc, (int32_t)v));
     if (lone) {
       labels[vin] = vin;
     } else if (l == INF && w.max_rounds > 0) {
@@ -1053,7 +1059,7 @@ __global__ void __launch_bounds__(BS) k_finalize(Ws w, int32_t *labels) {
       set_error(w.ctrl, ERR_LABEL);
       labels[vin] = -1;
     } else {
-      labels[vin] = l == w.rank[v] ? vin : w.order_in[l];  // a center is its own label
+      labels[vin] = w.order_in[l];  // the input id at the center's position (a center's own)
     }
   }
 }
@@ -1068,7 +1074,7 @@ static inline unsigned grid_for(int64_t items, unsigned cap) {
 }
 
 hipError_t launch_init(const Ws &w, const unsigned *lvl_init_cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_invert, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w);
+  hipLaunchKernelGGL(k_check_order, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w);
   hipLaunchKernelGGL(k_init, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w, lvl_init_cnt);
   hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, w);
   return hipGetLastError();

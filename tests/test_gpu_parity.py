@@ -176,6 +176,10 @@ def test_errors_leave_outputs_untouched(cc):
         with pytest.raises(cc.CCError) as ei:
             cc.cc_c4(gh, graphgen.permutation(g.n, 3), eps, labels=out)
         assert ei.value.code == cc.CC_ERR_INVALID_ARG
+    # the handle is still good after the rejected calls
+    good = graphgen.permutation(g.n, 4)
+    lab, _ = cc.cc_c4(gh, good, 0.5)
+    assert np.array_equal(lab, oracle.kwikcluster(g.off, g.col, good))
 
 
 @pytest.mark.parametrize("validate", [False, True])
