@@ -185,6 +185,12 @@ template <class T>
 __device__ inline void st_rel(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Relaxed device-scope atomic store: coherent across the XCDs like any
+// device-scope atomic, without the release's write-back of the whole L2.
+template <class T>
+__device__ inline void st_rlx(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 template <class T>
 __device__ inline T add_rlx(T *p, T v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -401,7 +401,12 @@ __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
 // ------------------------------------------------------------- select -----
 // Tile status word: bits 63..62 = 1 (aggregate) or 2 (inclusive prefix),
 // bits 61..0 = value.  Tiles are handed out in order by an atomic counter, so
-// a tile only ever waits for tiles that are already being processed.
+// a tile only ever waits for tiles that are already being processed.  The
+// word carries its value with its flag, so it is read and written with
+// relaxed device-scope atomics: nothing else needs ordering against it.  (A
+// release or acquire at device scope would write back or invalidate the
+// whole L2 of the XCD each time; the select_done flag is relaxed for the
+// same reason, and r_last, written before it, is read after the kernel.)
 
 // Decoupled look-back by one wave: lane l reads the status of tile j - l, so
 // each step covers 64 predecessors; the walk stops at the nearest inclusive
@@ -413,7 +418,7 @@ __device__ inline long long lookback(const Ws &w, unsigned t) {
   const int l = lane_id();
   while (j >= 0) {
     const long long idx = j - l;
-    const unsigned long long s = idx >= 0 ? ld_acq(&w.tstat[idx]) : (2ull << 62);
+    const unsigned long long s = idx >= 0 ? ld_rlx(&w.tstat[idx]) : (2ull << 62);
     const unsigned flag = (unsigned)(s >> 62);
     const unsigned long long incl = __ballot(flag == 2);
     const unsigned long long notready = __ballot(flag == 0);
@@ -454,7 +459,7 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
   if ((long long)blockIdx.x > need_pos / TSEL) return;
   for (;;) {
     if (threadIdx.x == 0) {
-      s_stop = ld_acq(&c->select_done);
+      s_stop = ld_rlx(&c->select_done);
       if (!s_stop) s_tile = atomicAdd(&c->tile_counter, 1u);
     }
     __syncthreads();
@@ -484,11 +489,11 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     if (threadIdx.x < 64) {  // wave 0 publishes and looks back
       long long excl = 0;
       if (t == 0) {
-        if (threadIdx.x == 0) st_rel(&w.tstat[0], (2ull << 62) | (unsigned long long)agg);
+        if (threadIdx.x == 0) st_rlx(&w.tstat[0], (2ull << 62) | (unsigned long long)agg);
       } else {
-        if (threadIdx.x == 0) st_rel(&w.tstat[t], (1ull << 62) | (unsigned long long)agg);
+        if (threadIdx.x == 0) st_rlx(&w.tstat[t], (1ull << 62) | (unsigned long long)agg);
         excl = lookback(w, t);
-        if (threadIdx.x == 0) st_rel(&w.tstat[t], (2ull << 62) | (unsigned long long)(excl + agg));
+        if (threadIdx.x == 0) st_rlx(&w.tstat[t], (2ull << 62) | (unsigned long long)(excl + agg));
       }
       if (threadIdx.x == 0) s_excl = excl;
     }
@@ -530,7 +535,7 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
           }
           if (r == B - 1) {
             c->r_last = base + k;
-            st_rel(&c->select_done, 1);
+            st_rlx(&c->select_done, 1);
           }
         }
         r++;
@@ -1035,7 +1040,9 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
     const unsigned long long p = (unsigned long long)(unsigned)round | (unsigned long long)(done != 0) << PROGRESS_DONE |
                                  (unsigned long long)(c->phase == PHASE_EXACT) << PROGRESS_EXACT |
                                  (unsigned long long)(c->error != 0) << PROGRESS_ERROR;
-    __hip_atomic_store(w.progress, p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    // relaxed: the host acts on this word alone and reads the rest of the
+    // state only after the stream has drained
+    __hip_atomic_store(w.progress, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
