@@ -222,11 +222,15 @@ def test_partial_run_max_rounds(cc, algo):
     """Stopping after k rounds gives the first k records of the full run; a
     vertex clustered by then already has its final label, the rest get -1."""
     g = graphgen.chung_lu(40_000, 2.1, 12.0, seed=51)
+    iso = np.diff(g.off) == 0
+    assert iso.sum() > 500  # isolated vertices are settled without a label until the end
     gh = upload(g)
     order = graphgen.permutation(g.n, 51)
     fn = cc.cc_c4 if algo == oracle.C4 else cc.cc_clusterwild
     full, stf = fn(gh, order, 0.5)
-    for k in (1, 3, stf.rounds - 1, stf.rounds, stf.rounds + 5):
+    assert np.array_equal(full[iso], np.flatnonzero(iso))  # each its own cluster
+    mixed = False
+    for k in (1, 3, stf.rounds // 2, stf.rounds - 1, stf.rounds, stf.rounds + 5):
         lab, st = fn(gh, order, 0.5, max_rounds=k)
         kk = min(k, stf.rounds)
         assert st.rounds == kk
@@ -236,5 +240,7 @@ def test_partial_run_max_rounds(cc, algo):
         assert np.array_equal(lab[done], full[done])
         left = int(stf.trace["n_i"][kk]) if kk < stf.rounds else 0
         assert int((~done).sum()) == left
+        mixed |= bool(done[iso].any() and (~done[iso]).any())
+    assert mixed  # some partial run stopped between isolated vertices
     with pytest.raises(cc.CCError):
         fn(gh, order, 0.5, max_rounds=-1)
