@@ -1050,16 +1050,21 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
 
 __global__ void __launch_bounds__(BS) k_finalize(Ws w, int32_t *labels) {
   const int64_t n = w.n;
-  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
-    // labels are indexed and valued in input ids
+  // by input id, so the labels are written in order; only the ids that are
+  // not isolated look at their internal state
+  for (int64_t vin = (int64_t)blockIdx.x * BS + threadIdx.x; vin < n; vin += (int64_t)gridDim.x * BS) {
+    const int32_t v = w.perm[vin];
+    if (v >= w.iso_start && w.max_rounds == 0) {  // a complete run settled every isolated vertex alone
+      labels[vin] = (int32_t)vin;
+      continue;
+    }
     const int32_t l = w.lab[v];
-    const int32_t vin = w.iperm[v];
-    // no label: a center k_select settled (an isolated vertex -- all of them
-    // once a run is complete; a partial run labels those it reached -- or a
-    // vertex whose bit it cleared), or still unclustered
-    const bool lone = l == INF && (v >= w.iso_start ? w.max_rounds == 0 : !unc_bit(w.unc, (int32_t)v));
+    // no label: a center k_select settled (an isolated vertex -- a partial
+    // run labels those it reached -- or a vertex whose bit it cleared), or
+    // still unclustered
+    const bool lone = l == INF && v < w.iso_start && !unc_bit(w.unc, v);
     if (lone) {
-      labels[vin] = vin;
+      labels[vin] = (int32_t)vin;
     } else if (l == INF && w.max_rounds > 0) {
       labels[vin] = -1;  // a partial run left v unclustered
     } else if (l < 0 || (int64_t)l >= n) {
