@@ -79,11 +79,25 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
   }
   __syncthreads();
   int64_t ent0 = s_ent;
+  // the tile's window of row prefixes, held in registers so that the next
+  // tile's window is in flight while this tile is processed
+  constexpr int NPW = (TW + 1 + BS - 1) / BS;
+  int64_t pw[NPW];
+  auto load_window = [&](int64_t e0) {
+#pragma unroll
+    for (int q = 0; q < NPW; q++) {
+      const int j = (int)threadIdx.x + q * BS;
+      const int64_t idx = e0 + j;
+      pw[q] = (j <= TW && idx < cnt) ? work[idx] : INT64_MAX;
+    }
+  };
+  load_window(ent0);
   for (int64_t s = s0; s < s1; s += TW) {
     const int64_t send = (s + TW) < s1 ? (s + TW) : s1;
-    for (int j = threadIdx.x; j <= TW; j += BS) {
-      const int64_t idx = ent0 + j;
-      lw[j] = idx < cnt ? work[idx] : INT64_MAX;
+#pragma unroll
+    for (int q = 0; q < NPW; q++) {
+      const int j = (int)threadIdx.x + q * BS;
+      if (j <= TW) lw[j] = pw[q];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -92,6 +106,7 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
     }
     __syncthreads();
     const int nent = s_nent;
+    if (s + TW < s1) load_window(ent0 + s_next);  // the next tile's window
     for (int j = threadIdx.x; j < nent; j += BS) {
       const int32_t v = list ? list[ent0 + j] : (int32_t)(ent0 + j);
       lv[j] = v;
