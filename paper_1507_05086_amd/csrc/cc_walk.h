@@ -75,7 +75,11 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
   const int64_t s1 = (s0 + per * TW) < total ? (s0 + per * TW) : total;
   if (threadIdx.x < 64) {
     const int64_t e = wave_find_entry(work, cnt, s0);
-    if (threadIdx.x == 0) s_ent = e;
+    if (threadIdx.x == 0) {
+      s_ent = e;
+      s_nent = 0;
+      s_next = 0;
+    }
   }
   __syncthreads();
   int64_t ent0 = s_ent;
@@ -94,19 +98,27 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
   load_window(ent0);
   for (int64_t s = s0; s < s1; s += TW) {
     const int64_t send = (s + TW) < s1 ? (s + TW) : s1;
+    // the window is sorted, so counting its entries below a bound is the
+    // upper-bound search: rows touched by this tile, and where the next starts
+    int c_rows = 0, c_next = 0;
 #pragma unroll
     for (int q = 0; q < NPW; q++) {
       const int j = (int)threadIdx.x + q * BS;
-      if (j <= TW) lw[j] = pw[q];
+      if (j <= TW) {
+        lw[j] = pw[q];
+        c_rows += pw[q] <= send - 1;
+        c_next += pw[q] <= s + TW;
+      }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      s_nent = lds_upper_bound(lw, TW + 1, send - 1);           // rows touched by this tile
-      s_next = (s + TW < s1) ? lds_upper_bound(lw, TW + 1, s + TW) - 1 : 0;
+    const int64_t w_rows = wave_sum((int64_t)c_rows), w_next = wave_sum((int64_t)c_next);
+    if (lane_id() == 0) {
+      atomicAdd(&s_nent, (int)w_rows);
+      atomicAdd(&s_next, (int)w_next);
     }
     __syncthreads();
     const int nent = s_nent;
-    if (s + TW < s1) load_window(ent0 + s_next);  // the next tile's window
+    const int next = (s + TW < s1) ? s_next - 1 : 0;
+    if (s + TW < s1) load_window(ent0 + next);  // the next tile's window
     for (int j = threadIdx.x; j < nent; j += BS) {
       const int32_t v = list ? list[ent0 + j] : (int32_t)(ent0 + j);
       lv[j] = v;
@@ -123,6 +135,10 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) {  // every thread has read them; the next tile counts afresh
+      s_nent = 0;
+      s_next = 0;
+    }
     Items it;
     it.edge = 0;
     it.vert = 0;
@@ -165,7 +181,7 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
       }
     }
     if constexpr (!std::is_same<typename std::decay<P>::type, NoPost>::value) post();
-    ent0 += s_next;
+    ent0 += next;
     __syncthreads();
   }
 }
