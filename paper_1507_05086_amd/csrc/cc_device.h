@@ -24,8 +24,8 @@ constexpr int BS = 256;             // threads per workgroup (4 wave64s)
 constexpr int WAVES = BS / 64;
 constexpr int IPT = 4;              // adjacency items per thread per tile
 constexpr int TW = BS * IPT;        // adjacency items per tile
-constexpr int SIPT = 16;            // pi positions per thread in the active-set scan
-constexpr int SEL_BS = 256;         // threads of an active-set scan workgroup
+constexpr int SIPT = 8;            // pi positions per thread in the active-set scan
+constexpr int SEL_BS = 512;         // threads of an active-set scan workgroup
 constexpr int TSEL = SEL_BS * SIPT; // pi positions per scan tile
 constexpr int32_t INF = 0x7fffffff;
 
