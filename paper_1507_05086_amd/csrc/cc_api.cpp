@@ -66,7 +66,7 @@ struct Workspace {
   uint32_t *unc = nullptr;
   uint8_t *state = nullptr, *flag = nullptr;
   int32_t *alist = nullptr, *clist = nullptr, *nlist = nullptr, *blist = nullptr;
-  int64_t *awork = nullptr, *cwork = nullptr, *nwork = nullptr;
+  int64_t *awork = nullptr, *cwork = nullptr;
   int32_t *rlist = nullptr, *xlist = nullptr, *plist = nullptr;
   int64_t *rwork = nullptr, *xwork = nullptr, *pwork = nullptr;
   RowInfo *ainfo = nullptr, *cinfo = nullptr;
@@ -146,7 +146,7 @@ namespace {
 
 void free_ws(Workspace &w) {
   void *ptrs[] = {w.rank, w.lab, w.ub, w.unc, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
-                  w.awork, w.cwork, w.nwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist, w.plist, w.pwork,
+                  w.awork, w.cwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist, w.plist, w.pwork,
                   w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf, w.label_buf, w.sched, w.mlp, w.ainfo, w.cinfo,
                   w.iorder, w.cost_size, w.cost_acc, w.dev_err};
   for (void *p : ptrs)
@@ -202,7 +202,6 @@ int32_t ensure_ws(cc_graph *g) {
   HIP_TRY(dalloc(&w.blist, n));
   HIP_TRY(dalloc(&w.awork, n));
   HIP_TRY(dalloc(&w.cwork, n));
-  HIP_TRY(dalloc(&w.nwork, n));
   HIP_TRY(dalloc(&w.ainfo, n));
   HIP_TRY(dalloc(&w.cinfo, n));
   w.rcap = g->n_hi + 1;
@@ -360,7 +359,6 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.blist = ws.blist;
   w.awork = ws.awork;
   w.cwork = ws.cwork;
-  w.nwork = ws.nwork;
   w.ainfo = ws.ainfo;
   w.cinfo = ws.cinfo;
   w.rlist = ws.rlist;

@@ -129,7 +129,7 @@ struct Ws {
   uint8_t *state, *flag;
   // lists
   int32_t *alist, *clist, *nlist, *blist, *rlist, *xlist, *plist;
-  int64_t *awork, *cwork, *nwork, *rwork, *xwork, *pwork;
+  int64_t *awork, *cwork, *rwork, *xwork, *pwork;
   RowInfo *ainfo, *cinfo;  // row info of alist / clist entries
   unsigned long long *racc;  // rescan accumulators (items covered << 32 | count), DITER * rcap
   int64_t rcap;         // capacity of one pass's rescan list
@@ -285,10 +285,6 @@ __device__ inline void wave_append_info(bool pred, int32_t v, RowInfo ri, unsign
   }
 }
 
-__device__ inline int64_t row_weight(const int64_t *off, int32_t v) {
-  const int64_t d = off[v + 1] - off[v];
-  return d > 0 ? d : 1;
-}
 
 // Largest i in [0, cnt) with work[i] <= s (work[0] = 0 <= s): a 64-ary search
 // by one wave, about log64(cnt) dependent loads.
@@ -325,6 +321,41 @@ struct StageBuf {
   unsigned long long base;
   int64_t sh[WAVES + 1];
 };
+
+// Staging buffer of bare ids for a list nobody walks edge-balanced: one
+// atomic reservation per flush, no weights and no work prefix.
+template <int CAP>
+struct IdBuf {
+  int32_t id[CAP];
+  int cnt;
+  unsigned long long base;
+};
+
+template <int CAP>
+__device__ inline void id_init(IdBuf<CAP> &b) {
+  if (threadIdx.x == 0) b.cnt = 0;
+  __syncthreads();
+}
+
+template <int CAP>
+__device__ inline void id_push(IdBuf<CAP> &b, int32_t v) {
+  b.id[atomicAdd(&b.cnt, 1)] = v;
+}
+
+// Collective: every thread of the workgroup calls it.
+template <int CAP>
+__device__ inline void id_flush(IdBuf<CAP> &b, unsigned long long *packc, int32_t *list) {
+  __syncthreads();
+  const int cnt = b.cnt;
+  if (cnt == 0) return;
+  if (threadIdx.x == 0) b.base = atomicAdd(packc, pk(0, cnt));
+  __syncthreads();
+  const int64_t slot0 = pk_cnt(b.base);
+  for (int i = threadIdx.x; i < cnt; i += BS) list[slot0 + i] = b.id[i];
+  __syncthreads();
+  if (threadIdx.x == 0) b.cnt = 0;
+  __syncthreads();
+}
 
 // Staging buffer whose entries also carry row info.
 template <int CAP>

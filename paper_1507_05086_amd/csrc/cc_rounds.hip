@@ -744,7 +744,7 @@ __global__ void __launch_bounds__(BS) k_resolve(Ws w) {
 
 // -------------------------------------------------------------- claim -----
 
-constexpr int CLAIM_CAP = 3 * TW;  // staged newly-clustered entries (a tile adds <= 2*TW)
+constexpr int CLAIM_CAP = 2 * TW;  // staged newly claimed vertices (a tile adds <= TW)
 
 __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   Ctrl *c = w.ctrl;
@@ -755,17 +755,12 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   const int64_t *work = c4 ? w.cwork : w.awork;
   const RowInfo *info = c4 ? w.cinfo : w.ainfo;
   __shared__ unsigned s_atom;
-  __shared__ StageBuf<CLAIM_CAP> sb;
+  __shared__ IdBuf<CLAIM_CAP> sb;
   if (threadIdx.x == 0) s_atom = 0;
-  stage_init(sb);
+  id_init(sb);
   lb_walk(
       list, work, pk_cnt(lp), pk_work(lp), w.off, w.col, nullptr, info,
       [&](Items &it) {
-        // every center is clustered this round; it goes to the newly list
-        // marked (~v): its row needs no peeling (below)
-#pragma unroll
-        for (int k = 0; k < IPT; k++)
-          if (it.vert >> k & 1) stage_push(sb, ~it.v[k], it.deg[k] > 0 ? it.deg[k] : 1);
         bool un[IPT];
 #pragma unroll
         for (int k = 0; k < IPT; k++) un[k] = (it.edge >> k & 1) && unc_bit(w.unc, it.u[k]);
@@ -786,7 +781,7 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
           if (elig[k] && it.val[k] < cur[k]) {
             const int32_t old = atomicMin(&w.lab[it.u[k]], it.val[k]);
             atom++;
-            if (old == INF) stage_push(sb, it.u[k], (int32_t)row_weight(w.off, it.u[k]));
+            if (old == INF) id_push(sb, it.u[k]);  // the newly claimed list
           }
         }
         if (atom) atomicAdd(&s_atom, atom);
@@ -794,9 +789,9 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
       NoEpilogue(),
       [&]() {
         __syncthreads();
-        if (sb.cnt > CLAIM_CAP - 2 * TW) stage_flush(sb, &c->n_pack, w.nlist, w.nwork);
+        if (sb.cnt > CLAIM_CAP - TW) id_flush(sb, &c->n_pack, w.nlist);
       });
-  stage_flush(sb, &c->n_pack, w.nlist, w.nwork);
+  id_flush(sb, &c->n_pack, w.nlist);
   if (threadIdx.x == 0 && s_atom) atomicAdd(&c->spread_atom[blockIdx.x & 63], (unsigned long long)s_atom);
 }
 
@@ -806,13 +801,15 @@ __device__ inline void hist_add(int *s_hist, int *g_hist, int d, int x) {
   else atomicAdd(&g_hist[d], x);
 }
 
-// The newly clustered leave the unclustered bitmap; ClusterWild! conflict
-// marks are counted; the scan tiles of this round are forgotten.  In the
-// exact phase the claimed vertices that still had unclustered neighbours go to
-// the peel list.  Centers do not: every unclustered neighbour of a center is
-// claimed in the same round (C4 claims all of them and no two centers are
-// adjacent; ClusterWild!'s active neighbours are centers themselves), so a
-// center's row has nobody left to peel; it only leaves the degree histogram.
+// The newly clustered -- the listed centers (C4's center list, ClusterWild!'s
+// active list) and the newly claimed -- leave the unclustered bitmap;
+// ClusterWild! conflict marks are counted; the scan tiles of this round are
+// forgotten.  In the exact phase the claimed vertices that still had
+// unclustered neighbours go to the peel list.  Centers do not: every
+// unclustered neighbour of a center is claimed in the same round (C4 claims
+// all of them and no two centers are adjacent; ClusterWild!'s active
+// neighbours are centers themselves), so a center's row has nobody left to
+// peel; it only leaves the degree histogram.
 __global__ void __launch_bounds__(BS) k_clear(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
@@ -820,17 +817,18 @@ __global__ void __launch_bounds__(BS) k_clear(Ws w) {
   __shared__ int s_hist[HLDS];
   for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
   stage_init(sp);
-  const int64_t nn = pk_cnt(c->n_pack);
   const bool cw = w.algo == ALGO_CW, exact = c->phase == PHASE_EXACT;
+  const int64_t nc = pk_cnt(cw ? c->a_pack : c->c_pack);
+  const int32_t *centers = cw ? w.alist : w.clist;
+  const int64_t nn = nc + pk_cnt(c->n_pack);
   unsigned conf = 0;
   const int64_t per = ((nn + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
   const int64_t i0 = (int64_t)blockIdx.x * per, i1 = i0 + per < nn ? i0 + per : nn;
   for (int64_t ib = i0; ib < i1; ib += BS) {
     const int64_t i = ib + threadIdx.x;
     if (i < i1) {
-      const int32_t e = w.nlist[i];
-      const bool center = e < 0;
-      const int32_t u = center ? ~e : e;
+      const bool center = i < nc;
+      const int32_t u = center ? centers[i] : w.nlist[i - nc];
       atomicAnd(&w.unc[u >> 5], ~(1u << (u & 31)));
       if (cw && w.flag[u]) {
         w.flag[u] = 0;
@@ -931,8 +929,9 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
     if (c->has_round) {
       const int phase_run = c->phase;  // phase the finished round ran in
       const bool c4 = w.algo == ALGO_C4;
-      const long long centers = (c4 ? pk_cnt(c->c_pack) : pk_cnt(c->a_pack)) + lone;
-      const long long newly = pk_cnt(c->n_pack) + lone;
+      const long long listed = c4 ? pk_cnt(c->c_pack) : pk_cnt(c->a_pack);  // centers in a list
+      const long long centers = listed + lone;
+      const long long newly = pk_cnt(c->n_pack) + listed + lone;
       const long long conf = c4 ? (long long)c->n_blocked : (long long)c->conflicts;
       if (c->round < w.trace_cap) {
         RoundRec r;
@@ -953,7 +952,7 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
       c->sum_claim += c4 ? (unsigned long long)pk_work(c->c_pack) : (unsigned long long)pk_work(c->a_pack);
       c->sum_rescan += resc;
       c->sum_peel += phase_run == PHASE_EXACT ? (unsigned long long)pk_work(c->p_pack) : 0ull;
-      c->sum_atomics += (unsigned long long)pk_cnt(c->n_pack);  // bitmap clears of the listed
+      c->sum_atomics += (unsigned long long)(pk_cnt(c->n_pack) + listed);  // bitmap clears of the listed
       c->sum_blocked += (unsigned long long)conf;
       c->feat_conf = c->b > 0 ? (float)conf / (float)c->b : 0.f;
       c->feat_claim = c->n_start > 0 ? (float)(newly - centers) / (float)c->n_start : 0.f;
