@@ -156,6 +156,42 @@ def test_repeat_and_streams(cc):
         assert np.array_equal(lab, outs[0][0]) and np.array_equal(b, outs[0][1])
 
 
+# ------------------------------------------------ seeded random sweep
+
+def _random_case(i):
+    """Case i of a seeded sweep: a graph family, a size from 1 to a few
+    thousand vertices (often with many isolated or low-degree vertices; every
+    eighth case a power-law graph of 40-80 thousand with hubs), an order and
+    an eps drawn log-uniformly from [0.05, 8]."""
+    rng = np.random.default_rng(1000 + i)
+    n = int(rng.integers(1, 4000))
+    kind = i % 4 if i % 8 != 7 else 4
+    if kind == 4:  # hubs: the lazy degree search, then the switch to exact degrees
+        g = graphgen.chung_lu(int(rng.integers(40_000, 80_000)), float(rng.uniform(2.0, 2.3)),
+                              float(rng.uniform(8.0, 16.0)), seed=2000 + i)
+    elif kind == 0:
+        g = graphgen.erdos_renyi(n, float(rng.uniform(0.2, 12.0)), seed=2000 + i)
+    elif kind == 1:
+        g = graphgen.chung_lu(n, float(rng.uniform(1.9, 2.8)), float(rng.uniform(1.0, 20.0)), seed=2000 + i)
+    elif kind == 2:
+        scale = max(1, int(np.log2(n)))
+        g = graphgen.rmat(scale, int(rng.integers(1, 16)), 0.57, 0.19, 0.19, seed=2000 + i)
+    else:
+        g = graphgen.erdos_renyi(n, float(rng.uniform(0.0, 1.5)), seed=2000 + i)  # mostly isolated vertices
+    eps = float(np.exp(rng.uniform(np.log(0.05), np.log(8.0))))
+    return g, graphgen.permutation(g.n, 3000 + i), eps
+
+
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+def test_random_sweep(cc, algo):
+    """Labels, round traces and costs against the oracle over 48 seeded cases
+    (every settled-vertex path: isolated, no neighbour left, listed)."""
+    for i in range(48):
+        g, order, eps = _random_case(i)
+        gh = upload(g)
+        check_against_oracle(algo, g, gh, order, eps)
+
+
 # ------------------------------------------------------------ errors
 
 def test_errors_leave_outputs_untouched(cc):
