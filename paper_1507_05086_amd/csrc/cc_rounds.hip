@@ -503,8 +503,9 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     // active vertex with no unclustered neighbour (degree 0, or an exact
     // remaining degree of 0) is a center that claims nobody and that no
     // other active vertex can see: it is settled here and never listed.  Its
-    // label stays unset; k_finalize recognises it (isolated and passed by the
-    // cursor, or its bit cleared with no label) and makes it its own center.
+    // label stays unset; k_finalize makes it its own center (an isolated
+    // vertex once the run is complete -- a partial run labels the isolated
+    // vertices it reaches -- or a vertex with its bit cleared and no label).
     int64_t wsum = 0;
     int cnt = 0, lone = 0;
     unsigned clears = 0;
@@ -549,10 +550,8 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     ctot &= 0xFFFFFFFFll;
     if (threadIdx.x == 0 && ctot > 0) s_base = atomicAdd(&c->a_pack, pk(wtot, ctot));
     if (threadIdx.x == 0 && ltot > 0) atomicAdd(&c->spread_lone[blockIdx.x & 63], (unsigned long long)ltot);
-    if (clears) {
-      const int64_t wc = wave_sum((int64_t)clears);
-      if (lane_id() == 0) atomicAdd(&c->spread_atom[blockIdx.x & 63], (unsigned long long)wc);
-    }
+    const int64_t wc = wave_sum((int64_t)clears);  // every lane takes part in the sum
+    if (lane_id() == 0 && wc) atomicAdd(&c->spread_atom[blockIdx.x & 63], (unsigned long long)wc);
     __syncthreads();
     if (ctot > 0) {
       int64_t slot = pk_cnt(s_base) + cpre, wpos = pk_work(s_base) + wpre;
