@@ -649,7 +649,9 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
 // active neighbour is a center, and a center once all of them are
 // non-centers.  Each sweep settles at least the lowest-ranked undecided
 // vertex, so it ends.
-__global__ void __launch_bounds__(BS) k_resolve(Ws w) {
+constexpr int RBS = 1024;  // one workgroup settles the blocked vertices
+
+__global__ void __launch_bounds__(RBS) k_resolve(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
   const int64_t nb = c->n_blocked;
@@ -660,21 +662,21 @@ __global__ void __launch_bounds__(BS) k_resolve(Ws w) {
     // conflict edges (a, u): u is an earlier-ranked active neighbour of a
     const int64_t ne = ne_all;
     for (int64_t iter = 0; iter <= nb; iter++) {
-      for (int64_t i = threadIdx.x; i < ne; i += BS) {
+      for (int64_t i = threadIdx.x; i < ne; i += RBS) {
         const int2 e = w.cedge[i];
         if (w.state[e.x] == ACTIVE && w.state[e.y] == CENTER) w.state[e.x] = NONCENTER;
       }
       __syncthreads();
-      for (int64_t i = threadIdx.x; i < nb; i += BS) w.flag[w.blist[i]] = 0;
+      for (int64_t i = threadIdx.x; i < nb; i += RBS) w.flag[w.blist[i]] = 0;
       __syncthreads();
-      for (int64_t i = threadIdx.x; i < ne; i += BS) {
+      for (int64_t i = threadIdx.x; i < ne; i += RBS) {
         const int2 e = w.cedge[i];
         if (w.state[e.x] == ACTIVE && w.state[e.y] == ACTIVE) w.flag[e.x] = 1;  // still waiting
       }
       __syncthreads();
       if (threadIdx.x == 0) s_any = 0;
       __syncthreads();
-      for (int64_t i0 = 0; i0 < nb; i0 += BS) {
+      for (int64_t i0 = 0; i0 < nb; i0 += RBS) {
         const int64_t i = i0 + threadIdx.x;
         int32_t a = 0;
         bool promote = false, waiting = false;
@@ -703,7 +705,7 @@ __global__ void __launch_bounds__(BS) k_resolve(Ws w) {
     for (int64_t iter = 0; iter <= nb; iter++) {
       if (threadIdx.x == 0) s_any = 0;
       __syncthreads();
-      for (int64_t i0 = 0; i0 < nb; i0 += BS) {
+      for (int64_t i0 = 0; i0 < nb; i0 += RBS) {
         const int64_t i = i0 + threadIdx.x;
         int32_t a = 0;
         bool promote = false;
@@ -738,7 +740,7 @@ __global__ void __launch_bounds__(BS) k_resolve(Ws w) {
       if (!s_any) break;
     }
   }
-  for (int64_t i = threadIdx.x; i < nb; i += BS) w.flag[w.blist[i]] = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += RBS) w.flag[w.blist[i]] = 0;
 }
 
 // -------------------------------------------------------------- claim -----
@@ -1095,7 +1097,7 @@ hipError_t launch_round(const Ws &w, hipStream_t s, const LaunchShape &ls) {
   if (w.algo == ALGO_C4) {
     hipLaunchKernelGGL(k_elect, dim3(ls.edge_grid), dim3(BS), 0, s, w);
     hipLaunchKernelGGL(k_classify, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
-    hipLaunchKernelGGL(k_resolve, dim3(1), dim3(BS), 0, s, w);
+    hipLaunchKernelGGL(k_resolve, dim3(1), dim3(RBS), 0, s, w);
   }
   hipLaunchKernelGGL(k_claim, dim3(ls.edge_grid), dim3(BS), 0, s, w);
   hipLaunchKernelGGL(k_clear, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
