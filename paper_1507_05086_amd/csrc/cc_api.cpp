@@ -426,7 +426,10 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   launched = kRoundGroup;
   for (;;) {
     const int64_t older = launched;
-    if (int32_t rc = launch_rounds(ws, w, ls, kRoundGroup, s)) return rc;
+    if (int32_t rc = launch_rounds(ws, w, ls, kRoundGroup, s)) {
+      (void)hipStreamSynchronize(s);  // nothing of this call may still write the progress word
+      return rc;
+    }
     launched += kRoundGroup;
     bool done = false;
     for (unsigned spin = 1;; spin++) {
@@ -448,7 +451,10 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
       std::this_thread::yield();
     }
     if (done) break;
-    if (launched > n + 2) return fail(CC_ERR_NO_PROGRESS, "round loop exceeded n+1 rounds");
+    if (launched > n + 2) {
+      (void)hipStreamSynchronize(s);
+      return fail(CC_ERR_NO_PROGRESS, "round loop exceeded n+1 rounds");
+    }
   }
   HIP_TRY(hipEventRecord(ev1, s));
   Ctrl hc;
