@@ -86,12 +86,12 @@ typedef struct cc_round_record {
 /* Optional statistics of a run (pass NULL to skip). */
 typedef struct cc_run_stats {
   int64_t rounds;        /* out: rounds executed */
-  int64_t scanned_elect; /* out: adjacency entries (+1 per isolated row) read by the C4 election */
-  int64_t scanned_claim; /* out: adjacency entries (+1 per isolated row) read by claims */
-  int64_t scanned_peel;  /* out: adjacency entries (+1 per isolated row) read by peeling */
+  int64_t scanned_elect; /* out: adjacency entries read by the C4 election (listed active rows) */
+  int64_t scanned_claim; /* out: adjacency entries read by claims (listed centers' rows) */
+  int64_t scanned_peel;  /* out: adjacency entries read by peeling */
   int64_t scanned_delta; /* out: adjacency entries read to refresh remaining degrees (Delta) */
   int64_t blocked;       /* out: sum of conflicts over rounds */
-  int64_t atomics;       /* out: atomic read-modify-writes (claims and degree decrements) */
+  int64_t atomics;       /* out: atomic read-modify-writes (claims, degree decrements, bit clears) */
   double loop_ms;        /* out: device time of the round loop (HIP events on `stream`) */
   int32_t policy_fallback; /* out: 1 if the learned policy fell back to the fixed rule */
   int32_t truncated;       /* out: 1 if more rounds ran than trace_capacity */

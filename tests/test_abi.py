@@ -37,3 +37,32 @@ def test_policy_validation_on_host():
     with pytest.raises(cc.CCError):
         cc.cc_set_eps_policy(7)
     cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The Python binding's ctypes structures have the sizes and field offsets
+    a C compiler gives the header's structures."""
+    import subprocess
+    import paper_1507_05086_amd as cc
+    structs = {"cc_round_record": cc._RoundRecord, "cc_run_stats": cc._RunStats,
+               "cc_batch_config": cc._BatchConfig}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cc.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c = {}
+    for line in out:
+        if line:
+            parts = line.split()
+            c[tuple(parts[:-1])] = int(parts[-1])
+    for cname, py in structs.items():
+        assert c[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert c[(cname, f)] == getattr(py, f).offset, (cname, f)
