@@ -17,7 +17,11 @@ def _ensure_native():
     """Build the in-tree libraries once if they are missing (CPU-only runs)."""
     lib = os.path.join(ROOT, "paper_1507_05086_amd", "libcc.so")
     if not os.path.exists(lib):
-        from paper_1507_05086_amd import build as ccbuild
+        import importlib.util
+        path = os.path.join(ROOT, "paper_1507_05086_amd", "build.py")
+        spec = importlib.util.spec_from_file_location("_cc_build", path)
+        ccbuild = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(ccbuild)  # not through the package: that would load libcc.so
         ccbuild.build()
 
 
