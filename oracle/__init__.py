@@ -29,8 +29,12 @@ TRACE_FIELDS = ("n_i", "delta_i", "b_i", "r_i", "centers", "claimed", "conflicts
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle (serial, portable -O2) into libcc_oracle.so."""
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC]
+    """Compile the oracle (serial, -O3 for any x86-64 CPU with AVX2 -- the
+    library travels to other hosts, so not -march=native; no fused
+    multiply-add contraction, so every floating-point step rounds as written)
+    into libcc_oracle.so."""
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-Wall",
+           "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -52,7 +56,7 @@ def _load():
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.orc_kwikcluster.argtypes = [i64, vp, vp, vp, vp]
     lib.orc_kwikcluster.restype = i32
-    lib.orc_bsp.argtypes = [i32, i64, vp, vp, vp, i64, vp, i64, vp, vp, i64]
+    lib.orc_bsp.argtypes = [i32, i64, vp, vp, vp, i64, vp, i64, vp, vp, i64, vp]
     lib.orc_bsp.restype = i64
     lib.orc_quantize_eps.argtypes = [ctypes.c_double]
     lib.orc_quantize_eps.restype = i64
@@ -78,6 +82,7 @@ class BSPResult:
     labels: np.ndarray
     rounds: int
     trace: np.ndarray  # structured array with TRACE_FIELDS
+    round_of: np.ndarray = None  # round in which each vertex was clustered (if asked for)
 
     def trace_dict(self, i: int) -> dict:
         return {f: int(self.trace[f][i]) for f in TRACE_FIELDS}
@@ -100,7 +105,8 @@ def quantize_eps(eps: float) -> int:
     return int(_load().orc_quantize_eps(eps))
 
 
-def bsp(algo: int, off, col, order, eps: float = 0.5, sched=None, trace_cap: int = 1 << 16) -> BSPResult:
+def bsp(algo: int, off, col, order, eps: float = 0.5, sched=None, trace_cap: int = 1 << 16,
+        with_round_of: bool = False) -> BSPResult:
     """Serial simulation of the BSP round loop (Algorithm 2), C4 or ClusterWild!."""
     off, po = _c(off, np.int64)
     col, pc = _c(col, np.int32)
@@ -113,11 +119,14 @@ def bsp(algo: int, off, col, order, eps: float = 0.5, sched=None, trace_cap: int
     else:
         sched, sp = _c(sched, np.int64)
         slen = len(sched)
+    round_of = np.full(n, -1, dtype=np.int32) if with_round_of else None
     rounds = _load().orc_bsp(algo, n, po, pc, pr, quantize_eps(eps), sp, slen,
-                             labels.ctypes.data, trace.ctypes.data, trace_cap)
+                             labels.ctypes.data, trace.ctypes.data, trace_cap,
+                             round_of.ctypes.data if with_round_of else None)
     if rounds < 0:
         raise ValueError(f"orc_bsp failed ({rounds})")
-    return BSPResult(labels=labels, rounds=int(rounds), trace=trace[:min(rounds, trace_cap)])
+    return BSPResult(labels=labels, rounds=int(rounds), trace=trace[:min(rounds, trace_cap)],
+                     round_of=round_of)
 
 
 def c4(off, col, order, eps=0.5, sched=None, trace_cap=1 << 16) -> BSPResult:

@@ -114,12 +114,13 @@ int64_t orc_quantize_eps(double eps) { return (int64_t)(eps * 1e6 + 0.5); }
  *   5. clustered vertices leave the graph (remaining degrees drop).
  * sched (optional, sched_len entries, each >= 1) replaces step 1's rule for
  * the first sched_len rounds with B_i = min(sched[i], n_i).
- * Writes labels (center vertex ids) and up to trace_cap round records.
+ * Writes labels (center vertex ids), up to trace_cap round records and, if
+ * round_of is given, the round in which each vertex was clustered.
  * Returns the number of rounds, or a negative ORC_E* code.
  */
 int64_t orc_bsp(int algo, int64_t n, const int64_t *off, const int32_t *col, const int32_t *order,
                 int64_t eps_q, const int64_t *sched, int64_t sched_len, int32_t *labels,
-                orc_round *trace, int64_t trace_cap) {
+                orc_round *trace, int64_t trace_cap, int32_t *round_of) {
   if ((algo != ORC_C4 && algo != ORC_CW) || n < 0 || eps_q <= 0) return ORC_EINVAL;
   for (int64_t i = 0; i < sched_len; i++)
     if (!sched || sched[i] < 1) return ORC_ETRACE;
@@ -207,6 +208,11 @@ int64_t orc_bsp(int algo, int64_t n, const int64_t *off, const int32_t *col, con
     for (int64_t i = 0; i < na; i++)
       if (center[active_list[i]]) labels[active_list[i]] = active_list[i];
     for (int64_t i = 0; i < ntouched; i++) labels[touched[i]] = order[best[touched[i]]];
+    if (round_of) {
+      for (int64_t i = 0; i < na; i++)
+        if (center[active_list[i]]) round_of[active_list[i]] = (int32_t)rounds;
+      for (int64_t i = 0; i < ntouched; i++) round_of[touched[i]] = (int32_t)rounds;
+    }
 
     /* 5. peel: clustered vertices leave; neighbours lose one degree each */
     for (int64_t i = 0; i < na; i++)

@@ -44,6 +44,10 @@ def test_path5_worked_example():
         assert r.trace["b_i"].tolist() == exp["b"]
         assert r.trace["delta_i"].tolist() == exp["delta"]
         assert r.trace["n_i"].tolist() == exp["n"]
+        assert r.trace["r_i"].tolist() == exp["r"]
+        assert r.trace["conflicts"].tolist() == exp["conflicts"]
+        assert r.trace["centers"].tolist() == exp["centers"]
+        assert r.trace["claimed"].tolist() == exp["claimed"]
         assert oracle.cost(g.off, g.col, r.labels) == exp["cost"]
 
 
@@ -315,3 +319,60 @@ def test_invalid_inputs_rejected():
         oracle.c4(g.off, g.col, np.arange(4, dtype=np.int32), sched=[2, 0])
     with pytest.raises(ValueError):
         oracle.cost(g.off, g.col, np.array([0, 1, 2, 9], dtype=np.int32))
+
+
+# ------------------------------- every trace field from its definition
+
+def _replay_checks(g, order, algo, eps):
+    """Re-derive every field of the oracle's round trace from its definition,
+    round by round, with plain full scans over the graph.  The only things
+    taken from the oracle are the round in which each vertex was clustered,
+    the labels and the trace itself."""
+    r = oracle.bsp(algo, g.off, g.col, order, eps, with_round_of=True)
+    n, lab, ro, tr = g.n, r.labels, r.round_of, r.trace
+    assert (ro >= 0).all() and (ro < r.rounds).all()
+    rank = np.empty(n, dtype=np.int64)
+    rank[order] = np.arange(n)
+    src = np.repeat(np.arange(n), np.diff(g.off))  # row of every adjacency entry
+    is_center = lab == np.arange(n)
+    prev_r = -1
+    for i in range(r.rounds):
+        unc = ro >= i  # unclustered when round i starts
+        assert tr["n_i"][i] == np.count_nonzero(unc)
+        # Delta_i: the largest number of unclustered neighbours of an unclustered vertex
+        live = unc[src] & unc[g.col]
+        deg = np.bincount(src[live], minlength=n)
+        assert tr["delta_i"][i] == (deg[unc].max() if unc.any() else 0)
+        # the active set: the unclustered vertices at pi positions (r_{i-1}, r_i]
+        ri = int(tr["r_i"][i])
+        assert unc[order[ri]]  # the last active vertex was still unclustered
+        assert not unc[order[:prev_r + 1]].any()  # every earlier position is settled
+        act = np.zeros(n, dtype=bool)
+        seg = order[prev_r + 1:ri + 1]
+        act[seg[unc[seg]]] = True
+        assert tr["b_i"][i] == np.count_nonzero(act)
+        # blocked: active vertices with an earlier-ranked active neighbour
+        e = act[src] & act[g.col] & (rank[g.col] < rank[src])
+        assert tr["conflicts"][i] == np.unique(src[e]).size
+        done = ro == i
+        ncent = np.count_nonzero(done & is_center)
+        assert tr["centers"][i] == ncent
+        assert tr["claimed"][i] == np.count_nonzero(done) - ncent
+        assert not (done & ~unc).any()
+        assert (ro[lab[done]] == i).all()  # a vertex joins a center made in the same round
+        if algo == oracle.CW:
+            assert is_center[act].all()  # ClusterWild! makes every active vertex a center
+        else:
+            assert not (done & is_center & ~act).any()  # C4's centers come from the active set
+        prev_r = ri
+    assert prev_r < n
+
+
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+@pytest.mark.parametrize("eps", [0.1, 0.5, 2.0])
+@pytest.mark.parametrize("family", ["rmat14", "chunglu5k"])
+def test_trace_fields_from_definitions(family, algo, eps):
+    g = (graphgen.rmat(14, 16, 0.57, 0.19, 0.19, seed=114) if family == "rmat14"
+         else graphgen.chung_lu(5000, 2.1, 16.0, seed=51))
+    order = graphgen.permutation(g.n, 7)
+    _replay_checks(g, order, algo, eps)
