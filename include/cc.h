@@ -102,6 +102,10 @@ typedef struct cc_run_stats {
   int64_t max_rounds;      /* in: 0 runs to completion; k > 0 stops after k rounds (single
                               graphs only): a partial run whose still-unclustered vertices
                               get label -1, used to measure one round from a replayed state */
+  int64_t fault_round;     /* in: 0 in normal use.  Test hook of the error path (single
+                              graphs): k > 0 makes the device report an error at the end of
+                              round k, as a failing round would, so the call returns
+                              CC_ERR_DEVICE with every kernel having exited normally */
 } cc_run_stats;
 
 /*

@@ -73,7 +73,7 @@ class _RunStats(ctypes.Structure):
                 ("loop_ms", ctypes.c_double), ("policy_fallback", ctypes.c_int32),
                 ("truncated", ctypes.c_int32), ("trace", ctypes.POINTER(_RoundRecord)),
                 ("trace_capacity", ctypes.c_int64), ("graph_rounds", ctypes.POINTER(ctypes.c_int32)),
-                ("max_rounds", ctypes.c_int64)]
+                ("max_rounds", ctypes.c_int64), ("fault_round", ctypes.c_int64)]
 
 
 class _BatchConfig(ctypes.Structure):
@@ -215,7 +215,8 @@ class RunStats:
     graph_rounds: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
 
 
-def _run(fn, graph: Graph, order, eps, labels=None, trace_capacity=1 << 14, stream=None, max_rounds=0):
+def _run(fn, graph: Graph, order, eps, labels=None, trace_capacity=1 << 14, stream=None, max_rounds=0,
+         fault_round=0):
     po, odev, _ko = _ptr(order, np.int32)
     if labels is None:
         if odev:
@@ -232,6 +233,7 @@ def _run(fn, graph: Graph, order, eps, labels=None, trace_capacity=1 << 14, stre
         st.trace = ctypes.cast(rec, ctypes.POINTER(_RoundRecord))
         st.trace_capacity = trace_capacity
     st.max_rounds = int(max_rounds)
+    st.fault_round = int(fault_round)
     gr = np.zeros(max(graph.num_graphs, 1), dtype=np.int32)
     st.graph_rounds = gr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     _check(fn(graph.handle, po, float(eps), pl, ctypes.byref(st), flags, _stream(stream, order, labels)))
@@ -249,16 +251,17 @@ def _run(fn, graph: Graph, order, eps, labels=None, trace_capacity=1 << 14, stre
 
 
 def cc_c4(graph: Graph, order, eps: float = 0.5, labels=None, trace_capacity: int = 1 << 14, stream=None,
-          max_rounds: int = 0):
+          max_rounds: int = 0, fault_round: int = 0):
     """C4 (labels equal KwikCluster's under the same order).  Returns (labels, RunStats).
-    max_rounds > 0 stops after that many rounds (unclustered vertices get -1)."""
-    return _run(_lib.cc_c4, graph, order, eps, labels, trace_capacity, stream, max_rounds)
+    max_rounds > 0 stops after that many rounds (unclustered vertices get -1);
+    fault_round > 0 is the error-path test hook of cc_run_stats."""
+    return _run(_lib.cc_c4, graph, order, eps, labels, trace_capacity, stream, max_rounds, fault_round)
 
 
 def cc_clusterwild(graph: Graph, order, eps: float = 0.5, labels=None, trace_capacity: int = 1 << 14,
-                   stream=None, max_rounds: int = 0):
+                   stream=None, max_rounds: int = 0, fault_round: int = 0):
     """ClusterWild!.  Returns (labels, RunStats)."""
-    return _run(_lib.cc_clusterwild, graph, order, eps, labels, trace_capacity, stream, max_rounds)
+    return _run(_lib.cc_clusterwild, graph, order, eps, labels, trace_capacity, stream, max_rounds, fault_round)
 
 
 def cc_cost(graph: Graph, labels, stream=None) -> np.ndarray:

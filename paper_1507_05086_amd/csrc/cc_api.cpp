@@ -77,6 +77,7 @@ struct Workspace {
   int64_t hist_len = 0;
   int2 *cedge = nullptr;
   int64_t cedge_cap = 0;
+  int32_t *bpos = nullptr, *bpend = nullptr, *bdec = nullptr, *bdep = nullptr, *bq = nullptr, *bradj = nullptr;
   unsigned long long *tstat = nullptr;
   int64_t tstat_cap = 0;
   Ctrl *ctrl = nullptr;
@@ -148,7 +149,7 @@ void free_ws(Workspace &w) {
   void *ptrs[] = {w.rank, w.lab, w.ub, w.unc, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
                   w.awork, w.cwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist, w.plist, w.pwork,
                   w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf, w.label_buf, w.sched, w.mlp, w.ainfo, w.cinfo,
-                  w.iorder, w.cost_size, w.cost_acc, w.dev_err};
+                  w.iorder, w.cost_size, w.cost_acc, w.dev_err, w.bpos, w.bpend, w.bdec, w.bdep, w.bq, w.bradj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (w.host_flags) (void)hipHostFree(w.host_flags);
@@ -217,6 +218,12 @@ int32_t ensure_ws(cc_graph *g) {
   HIP_TRY(dalloc(&w.hist, (size_t)w.hist_len));
   w.cedge_cap = n > (1 << 20) ? n : (1 << 20);
   HIP_TRY(dalloc(&w.cedge, (size_t)w.cedge_cap));
+  HIP_TRY(dalloc(&w.bpos, n));
+  HIP_TRY(dalloc(&w.bpend, n));
+  HIP_TRY(dalloc(&w.bdec, n));
+  HIP_TRY(dalloc(&w.bdep, n + 1));
+  HIP_TRY(dalloc(&w.bq, n));
+  HIP_TRY(dalloc(&w.bradj, (size_t)w.cedge_cap));
   w.tstat_cap = n / TSEL + 4096 + 2;
   HIP_TRY(dalloc(&w.tstat, (size_t)w.tstat_cap));
   HIP_TRY(hipMemset(w.tstat, 0, sizeof(unsigned long long) * (size_t)w.tstat_cap));
@@ -297,8 +304,11 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   if (stats && stats->trace_capacity > 0 && !stats->trace)
     return fail(CC_ERR_INVALID_ARG, "stats->trace is NULL but trace_capacity > 0");
   if (stats && stats->max_rounds < 0) return fail(CC_ERR_INVALID_ARG, "stats->max_rounds must be >= 0");
+  if (stats && stats->fault_round < 0) return fail(CC_ERR_INVALID_ARG, "stats->fault_round must be >= 0");
   if (stats && stats->max_rounds > 0 && g->num_graphs != 1)
     return fail(CC_ERR_INVALID_ARG, "max_rounds applies to single graphs only");
+  if (stats && stats->fault_round > 0 && g->num_graphs != 1)
+    return fail(CC_ERR_INVALID_ARG, "fault_round applies to single graphs only");
   if (g->num_graphs != 1) return run_batch(g, algo, order, eps, labels, stats, flags, s);
   Policy pol;
   {
@@ -374,6 +384,12 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.hist = ws.hist;
   w.cedge = ws.cedge;
   w.cedge_cap = ws.cedge_cap;
+  w.bpos = ws.bpos;
+  w.bpend = ws.bpend;
+  w.bdec = ws.bdec;
+  w.bdep = ws.bdep;
+  w.bq = ws.bq;
+  w.bradj = ws.bradj;
   w.tstat = ws.tstat;
   w.tstat_cap = ws.tstat_cap;
   w.ctrl = ws.ctrl;
@@ -389,9 +405,13 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.eps_min = (float)pol.eps_min;
   w.eps_max = (float)pol.eps_max;
   w.max_rounds = stats ? stats->max_rounds : 0;
+  w.fault_round = stats ? stats->fault_round : 0;
   w.progress = ws.progress_dev;
 
-  // init: the permutation is checked before any kernel indexes with it
+  // init.  The permutation check needs no host round trip: an entry out of
+  // range is never used as an index, and a failed check sets the device
+  // error, which ends the run in its first k_close; every later kernel of
+  // the call then returns at once.
   __atomic_store_n(ws.progress, 0ull, __ATOMIC_RELEASE);  // nothing of this handle is in flight
   HIP_TRY(hipMemsetAsync(ws.ctrl, 0, sizeof(Ctrl), s));
   HIP_TRY(hipMemsetAsync(ws.state, 0, (size_t)n, s));  // k_check_order marks the vertices pi names
@@ -399,11 +419,6 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   if (g->lvl_total > 0)
     HIP_TRY(hipMemcpyAsync(ws.lvl, g->lvl_init, sizeof(int32_t) * (size_t)g->lvl_total, hipMemcpyDeviceToDevice, s));
   HIP_TRY(launch_init(w, g->lvl_cnt0, s));
-  HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (ws.host_flags[1] == ERR_PERM)
-    return fail(CC_ERR_NOT_PERMUTATION, "order is not a permutation of 0..n-1");
-  if (ws.host_flags[1]) return fail(CC_ERR_DEVICE, "device error during initialisation");
 
   LaunchShape ls{512, 1024, 512, 0, 0};
   int64_t launched = 0;
@@ -459,21 +474,23 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   HIP_TRY(hipEventRecord(ev1, s));
   Ctrl hc;
   HIP_TRY(hipMemcpyAsync(&hc, ws.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  int32_t *d_labels = (flags & CC_OUTPUT_ON_DEVICE) ? labels : ws.label_buf;
-  HIP_TRY(launch_finalize(w, d_labels, s));
+  // labels go to the workspace first and reach the caller only on success,
+  // so a failed run leaves the caller's buffer untouched
+  HIP_TRY(launch_finalize(w, ws.label_buf, s));
   HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (hc.error) {  // the finalize pass above wrote nothing the caller may use
+  if (hc.error) {
     const int e = hc.error;
+    if (e == ERR_PERM) return fail(CC_ERR_NOT_PERMUTATION, "order is not a permutation of 0..n-1");
     if (e == ERR_NO_PROGRESS) return fail(CC_ERR_NO_PROGRESS, "round loop made no progress");
     if (e == ERR_OVERFLOW) return fail(CC_ERR_DEVICE, "a device work list overflowed");
+    if (e == ERR_INJECTED) return fail(CC_ERR_DEVICE, "device error injected by stats->fault_round");
     return fail(CC_ERR_DEVICE, "device error " + std::to_string(e) + " in the round loop");
   }
   if (ws.host_flags[0]) return fail(CC_ERR_DEVICE, "device error " + std::to_string(ws.host_flags[0]) + " while finishing");
-  if (!(flags & CC_OUTPUT_ON_DEVICE)) {
-    HIP_TRY(hipMemcpyAsync(labels, ws.label_buf, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
+  HIP_TRY(hipMemcpyAsync(labels, ws.label_buf, sizeof(int32_t) * (size_t)n,
+                         (flags & CC_OUTPUT_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   if (stats) {
     stats->rounds = hc.round;
     if (stats->graph_rounds) stats->graph_rounds[0] = (int32_t)hc.round;

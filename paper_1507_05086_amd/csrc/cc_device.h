@@ -40,7 +40,7 @@ constexpr int HLDS = 256;          // degree-histogram bins kept per workgroup i
 __host__ __device__ inline float band_factor(int pass) { return pass == 0 ? 0.7f : (pass == 1 ? 0.3f : 0.05f); }
 enum : int { ALGO_C4 = 0, ALGO_CW = 1 };
 enum : int { POL_FIXED = 0, POL_LEARNED = 1, POL_TRACE = 2 };
-enum : int { ERR_NONE = 0, ERR_PERM = 5, ERR_NO_PROGRESS = 8, ERR_OVERFLOW = 11, ERR_LABEL = 12 };
+enum : int { ERR_NONE = 0, ERR_PERM = 5, ERR_NO_PROGRESS = 8, ERR_OVERFLOW = 11, ERR_LABEL = 12, ERR_INJECTED = 13 };
 enum : int { PHASE_LAZY = 0, PHASE_EXACT = 1 };
 
 // A list is packed in one 64-bit counter: (total weight << 31) | count, so a
@@ -135,6 +135,11 @@ struct Ws {
   int64_t rcap;         // capacity of one pass's rescan list
   int2 *cedge;
   int64_t cedge_cap;
+  // C4's blocked vertices (k_resolve): the blocked index of a vertex (by
+  // vertex id), and per blocked index its undecided earlier blocked
+  // neighbours, its decision, the range of its later blocked neighbours in
+  // bradj, and the queue of decided indices
+  int32_t *bpos, *bpend, *bdec, *bdep, *bq, *bradj;
   unsigned long long *tstat;
   int64_t tstat_cap;
   // bound buckets
@@ -154,6 +159,7 @@ struct Ws {
   const float *mlp;     // LEARNED: 6-64-1 weights (device)
   float eps_min, eps_max;
   int64_t max_rounds;   // > 0: stop after this many rounds (partial run)
+  int64_t fault_round;  // > 0: test hook, the loop reports a device error after this round
   // progress word in pinned host memory, written by k_close at the end of
   // every round: rounds finished (bits 0..31), done (32), exact phase (33),
   // error (34)

@@ -645,101 +645,181 @@ __global__ void __launch_bounds__(BS) k_classify(Ws w) {
   stage_flush(sb, &c->c_pack, w.clist, w.cwork, nullptr, w.cinfo, sb.info);
 }
 
-// One workgroup: a blocked vertex is a non-center as soon as an earlier
-// active neighbour is a center, and a center once all of them are
-// non-centers.  Each sweep settles at least the lowest-ranked undecided
-// vertex, so it ends.
-constexpr int RBS = 1024;  // one workgroup settles the blocked vertices
+// One workgroup settles the blocked vertices: the greedy MIS of G[A] in pi
+// order restricted to them (rule 1).  A blocked vertex is a non-center as soon
+// as an earlier active neighbour is a center, and a center once every earlier
+// active neighbour is a non-center.
+constexpr int RBS = 1024;
+
+__device__ inline void mark_decided(Ws &w, int32_t i, unsigned *tail) {
+  const unsigned q = atomicAdd(tail, 1u);
+  w.bq[q] = i;
+}
+
+// The conflict edges are listed: build the dependence graph among the blocked
+// vertices (edge (a, u): a waits for u) and settle it from the vertices whose
+// earlier neighbours are all decided, level by level.  Every blocked vertex
+// enters the queue once, when it is decided, and then walks its later
+// neighbours once: O(blocked + conflict edges) work, one barrier per level.
+__device__ void resolve_listed(Ws &w, Ctrl *c, int64_t nb, int64_t ne) {
+  __shared__ unsigned s_tail;
+  __shared__ int64_t sh[RBS / 64 + 1];
+  __shared__ int64_t s_carry;
+  const int64_t total_dep = ne;  // upper bound of the dependence edges
+  if (threadIdx.x == 0) {
+    s_tail = 0;
+    s_carry = 0;
+  }
+  for (int64_t i = threadIdx.x; i < nb; i += RBS) {
+    w.bpos[w.blist[i]] = (int32_t)i;
+    w.bpend[i] = 0;
+    w.bdec[i] = 0;
+    w.bdep[i] = 0;
+  }
+  __syncthreads();
+  // an earlier neighbour that is a center already (a root) decides a at
+  // once; an earlier blocked one is a dependence
+  for (int64_t e = threadIdx.x; e < ne; e += RBS) {
+    const int2 ed = w.cedge[e];
+    const int32_t ia = w.bpos[ed.x];
+    if (w.state[ed.y] == CENTER) {
+      w.bdec[ia] = 2;
+    } else {
+      atomicAdd(&w.bpend[ia], 1);
+      atomicAdd(&w.bdep[w.bpos[ed.y]], 1);
+    }
+  }
+  __syncthreads();
+  // inclusive prefix of the dependents' counts: bdep[i] = end of i's range
+  for (int64_t i0 = 0; i0 < nb; i0 += RBS) {
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t x = i < nb ? w.bdep[i] : 0;
+    int64_t tot;
+    const int64_t pre = wg_excl_scan<RBS>(x, &tot, sh) + s_carry;
+    if (i < nb) w.bdep[i] = (int32_t)(pre + x);
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += tot;
+    __syncthreads();
+  }
+  if (s_carry > total_dep) {  // cannot happen: every dependence is a listed edge
+    if (threadIdx.x == 0) set_error(c, ERR_OVERFLOW);
+    return;
+  }
+  const int64_t ndep = s_carry;
+  // fill from the ends down: afterwards bdep[i] = start of i's range
+  for (int64_t e = threadIdx.x; e < ne; e += RBS) {
+    const int2 ed = w.cedge[e];
+    if (w.state[ed.y] != CENTER) {
+      const int32_t slot = atomicSub(&w.bdep[w.bpos[ed.y]], 1) - 1;
+      w.bradj[slot] = w.bpos[ed.x];
+    }
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < nb; i += RBS) {
+    if (w.bdec[i] == 2) {
+      mark_decided(w, (int32_t)i, &s_tail);
+    } else if (w.bpend[i] == 0) {
+      w.bdec[i] = 1;
+      mark_decided(w, (int32_t)i, &s_tail);
+    }
+  }
+  __syncthreads();
+  int64_t h0 = 0;
+  for (int64_t level = 0; level <= nb; level++) {
+    const int64_t h1 = s_tail;  // the decided indices this level walks
+    __syncthreads();            // every thread has read it before any appends
+    if (h0 >= h1) break;
+    for (int64_t q = h0 + threadIdx.x; q < h1; q += RBS) {
+      const int32_t x = w.bq[q];
+      const bool center = w.bdec[x] == 1;
+      const int64_t d0 = w.bdep[x], d1 = x + 1 < nb ? w.bdep[x + 1] : ndep;
+      for (int64_t d = d0; d < d1; d++) {
+        const int32_t y = w.bradj[d];
+        if (center) {
+          if (atomicCAS(&w.bdec[y], 0, 2) == 0) mark_decided(w, y, &s_tail);
+        } else if (atomicSub(&w.bpend[y], 1) == 1) {
+          if (atomicCAS(&w.bdec[y], 0, 1) == 0) mark_decided(w, y, &s_tail);
+        }
+      }
+    }
+    __syncthreads();
+    h0 = h1;
+  }
+  for (int64_t i0 = 0; i0 < nb; i0 += RBS) {
+    const int64_t i = i0 + threadIdx.x;
+    int32_t a = 0;
+    bool promote = false;
+    if (i < nb) {
+      a = w.blist[i];
+      const int d = w.bdec[i];
+      if (d == 1) promote = true;
+      else w.state[a] = NONCENTER;
+      if (d == 0) set_error(c, ERR_NO_PROGRESS);  // every blocked vertex is decided by now
+    }
+    RowInfo ri{0, 0, 0};
+    if (promote) {
+      ri = RowInfo{w.off[a], (int32_t)(w.off[a + 1] - w.off[a]), w.rank[a]};
+      w.state[a] = CENTER;
+      w.lab[a] = ri.rank;
+    }
+    wave_append_info(promote, a, ri, &c->c_pack, w.clist, w.cwork, w.cinfo);
+  }
+}
+
+// Too many conflict edges to list: sweep the rows of the blocked vertices
+// until nothing changes (every earlier-ranked unclustered neighbour of an
+// active vertex is active).  Each sweep settles at least the lowest-ranked
+// undecided vertex.
+__device__ void resolve_rows(Ws &w, Ctrl *c, int64_t nb) {
+  __shared__ int s_any;
+  for (int64_t iter = 0; iter <= nb; iter++) {
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    for (int64_t i0 = 0; i0 < nb; i0 += RBS) {
+      const int64_t i = i0 + threadIdx.x;
+      int32_t a = 0;
+      bool promote = false;
+      if (i < nb) {
+        a = w.blist[i];
+        if (w.state[a] == ACTIVE) {
+          const int32_t ra = w.rank[a];
+          bool center_before = false, undecided_before = false;
+          for (int64_t e = w.off[a]; e < w.off[a + 1] && !center_before; e++) {
+            const int32_t u = w.col[e];
+            if (!unc_bit(w.unc, u)) continue;
+            const uint8_t su = w.state[u];
+            if ((su == CENTER || su == ACTIVE) && w.rank[u] < ra) {
+              if (su == CENTER) center_before = true;
+              else undecided_before = true;
+            }
+          }
+          if (center_before) w.state[a] = NONCENTER;
+          else if (!undecided_before) promote = true;
+          else s_any = 1;
+        }
+      }
+      RowInfo ri{0, 0, 0};
+      if (promote) {
+        ri = RowInfo{w.off[a], (int32_t)(w.off[a + 1] - w.off[a]), w.rank[a]};
+        w.state[a] = CENTER;
+        w.lab[a] = ri.rank;
+      }
+      wave_append_info(promote, a, ri, &c->c_pack, w.clist, w.cwork, w.cinfo);
+    }
+    __syncthreads();
+    if (!s_any) break;
+  }
+}
 
 __global__ void __launch_bounds__(RBS) k_resolve(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
   const int64_t nb = c->n_blocked;
   if (nb == 0) return;
-  const int64_t ne_all = c->n_cedges;
-  __shared__ int s_any;
-  if (ne_all <= w.cedge_cap) {
-    // conflict edges (a, u): u is an earlier-ranked active neighbour of a
-    const int64_t ne = ne_all;
-    for (int64_t iter = 0; iter <= nb; iter++) {
-      for (int64_t i = threadIdx.x; i < ne; i += RBS) {
-        const int2 e = w.cedge[i];
-        if (w.state[e.x] == ACTIVE && w.state[e.y] == CENTER) w.state[e.x] = NONCENTER;
-      }
-      __syncthreads();
-      for (int64_t i = threadIdx.x; i < nb; i += RBS) w.flag[w.blist[i]] = 0;
-      __syncthreads();
-      for (int64_t i = threadIdx.x; i < ne; i += RBS) {
-        const int2 e = w.cedge[i];
-        if (w.state[e.x] == ACTIVE && w.state[e.y] == ACTIVE) w.flag[e.x] = 1;  // still waiting
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) s_any = 0;
-      __syncthreads();
-      for (int64_t i0 = 0; i0 < nb; i0 += RBS) {
-        const int64_t i = i0 + threadIdx.x;
-        int32_t a = 0;
-        bool promote = false, waiting = false;
-        if (i < nb) {
-          a = w.blist[i];
-          if (w.state[a] == ACTIVE) {
-            if (w.flag[a] == 0) promote = true;
-            else waiting = true;
-          }
-        }
-        RowInfo ri{0, 0, 0};
-        if (promote) {
-          ri = RowInfo{w.off[a], (int32_t)(w.off[a + 1] - w.off[a]), w.rank[a]};
-          w.state[a] = CENTER;
-          w.lab[a] = ri.rank;
-        }
-        if (waiting) s_any = 1;
-        wave_append_info(promote, a, ri, &c->c_pack, w.clist, w.cwork, w.cinfo);
-      }
-      __syncthreads();
-      if (!s_any) break;
-    }
-  } else {
-    // too many conflict edges to list: rescan the rows of the blocked vertices
-    // (every earlier-ranked unclustered neighbour of an active vertex is active)
-    for (int64_t iter = 0; iter <= nb; iter++) {
-      if (threadIdx.x == 0) s_any = 0;
-      __syncthreads();
-      for (int64_t i0 = 0; i0 < nb; i0 += RBS) {
-        const int64_t i = i0 + threadIdx.x;
-        int32_t a = 0;
-        bool promote = false;
-        if (i < nb) {
-          a = w.blist[i];
-          if (w.state[a] == ACTIVE) {
-            const int32_t ra = w.rank[a];
-            bool center_before = false, undecided_before = false;
-            for (int64_t e = w.off[a]; e < w.off[a + 1] && !center_before; e++) {
-              const int32_t u = w.col[e];
-              if (!unc_bit(w.unc, u)) continue;
-              const uint8_t su = w.state[u];
-              if ((su == CENTER || su == ACTIVE) && w.rank[u] < ra) {
-                if (su == CENTER) center_before = true;
-                else undecided_before = true;
-              }
-            }
-            if (center_before) w.state[a] = NONCENTER;
-            else if (!undecided_before) promote = true;
-            else s_any = 1;
-          }
-        }
-        RowInfo ri{0, 0, 0};
-        if (promote) {
-          ri = RowInfo{w.off[a], (int32_t)(w.off[a + 1] - w.off[a]), w.rank[a]};
-          w.state[a] = CENTER;
-          w.lab[a] = ri.rank;
-        }
-        wave_append_info(promote, a, ri, &c->c_pack, w.clist, w.cwork, w.cinfo);
-      }
-      __syncthreads();
-      if (!s_any) break;
-    }
-  }
+  const int64_t ne = c->n_cedges;
+  if (ne <= w.cedge_cap) resolve_listed(w, c, nb, ne);
+  else resolve_rows(w, c, nb);
+  __syncthreads();
   for (int64_t i = threadIdx.x; i < nb; i += RBS) w.flag[w.blist[i]] = 0;
 }
 
@@ -962,6 +1042,7 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
       c->n_rem = c->n_start - newly;
       c->round += 1;
       if (c->round > w.n + 1) set_error(c, ERR_NO_PROGRESS);
+      if (w.fault_round > 0 && c->round == w.fault_round) set_error(c, ERR_INJECTED);
       // Delta_{i+1} (lazy search, or the exact histogram below)
       long long d = 0;
       if (phase_run == PHASE_LAZY) {

@@ -12,10 +12,7 @@ batch sizes B_0..B_{i-1} through the TRACE policy; the rest of the run then
 uses the fixed rule with each candidate eps_k in {2^(k/2) / 16 : k = 0..16}, and
 the candidate whose whole run is fastest is the target eps* (the replayed
 prefix is the same for every candidate, so comparing whole runs compares the
-remainders).  A one-round look-ahead (most vertices clustered per microsecond
-of round i) is also available; it is myopic: it favours very large rounds,
-whose conflict resolution grows faster than their work.  Regression target:
-ln eps*.
+remainders).  Regression target: ln eps*.
 
 States come from runs of the fixed rule at several eps and, in later passes,
 from runs of the policy being trained (so it also learns the states it visits
@@ -48,14 +45,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def fixed_b(eps: float, n: int, delta: int) -> int:
-    """The batch-size rule of the library (eps quantised to millionths)."""
-    if delta <= 0:
-        return n
-    q = int(eps * 1e6 + 0.5)
-    return min(max((q * n + 1_000_000 * delta - 1) // (1_000_000 * delta), 1), n)
-
-
 def trace_features(trace, eps_call: float) -> np.ndarray:
     """Feature rows of every recorded round, as the round loop forms them."""
     n = len(trace)
@@ -74,20 +63,10 @@ def trace_features(trace, eps_call: float) -> np.ndarray:
     return X
 
 
-def group_starts(limit: int):
-    """Rounds whose timing spans a host synchronisation of the round loop
-    (it launches rounds in groups of 4, 8, 16, 32, then 64)."""
-    out, acc, g = set(), 0, 4
-    while acc <= limit:
-        acc += g
-        out.update((acc - 1, acc, acc + 1))
-        g = min(g * 2, 64)
-    return out
-
-
 def pick_rounds(rounds: int, count: int, rng) -> list:
-    bad = group_starts(rounds + 64)
-    pool = [i for i in range(rounds - 1) if i not in bad]
+    """States to label: rounds before the last one (a rollout times a whole
+    remaining run, so no round is special to the host's grouping of rounds)."""
+    pool = list(range(rounds - 1))
     if len(pool) <= count:
         return pool
     # half spread evenly in log(i + 1), half uniform
@@ -96,33 +75,6 @@ def pick_rounds(rounds: int, count: int, rng) -> list:
     rest = [r for r in pool if r not in pick]
     pick.update(rng.choice(rest, size=min(len(rest), count - len(pick)), replace=False).tolist())
     return sorted(pick)
-
-
-def lookahead(cc, gh, order, trace, i: int, repeats: int = 2):
-    """ln eps* of the state before round i of `trace` (see the module docstring)."""
-    n_i, d_i = int(trace["n_i"][i]), int(trace["delta_i"][i])
-    prefix = np.asarray(trace["b_i"][:i], np.int64)
-    by_b = {}
-    for e in CANDIDATES:
-        by_b.setdefault(fixed_b(e, n_i, d_i), []).append(e)
-    best, best_score = None, -1.0
-    for b, eps_list in by_b.items():
-        cc.cc_set_eps_policy(cc.CC_EPS_TRACE, np.concatenate([prefix, [b]]).astype(np.int64))
-        t_best, done = None, 0
-        for _ in range(repeats):
-            _, st = cc.cc_c4(gh, order, 0.5, labels=_scratch_labels(order), trace_capacity=i + 2,
-                             max_rounds=i + 1)
-            rec = st.trace[i]
-            if int(rec["n_i"]) != n_i or int(rec["delta_i"]) != d_i or int(rec["b_i"]) != b:
-                raise RuntimeError(f"replay diverged at round {i}")
-            done = int(rec["centers"]) + int(rec["claimed"])
-            t = int(rec["t_ns"])
-            t_best = t if t_best is None else min(t_best, t)
-        score = done / max(t_best, 1)
-        if score > best_score:
-            best_score, best = score, eps_list
-    cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
-    return float(np.mean(np.log(best)))
 
 
 def rollout(cc, gh, order, trace, i: int, repeats: int = 2):
@@ -154,7 +106,7 @@ def _scratch_labels(order):
     return _lab_cache[key]
 
 
-def collect(cc, gh, order, eps_bases, per_run: int, rng, weights=None, label="rollout"):
+def collect(cc, gh, order, eps_bases, per_run: int, rng, weights=None):
     """(X, t) samples from runs of the fixed rule at each eps in eps_bases
     and, if `weights` is given, of that policy."""
     Xs, ts = [], []
@@ -170,7 +122,7 @@ def collect(cc, gh, order, eps_bases, per_run: int, rng, weights=None, label="ro
         X = trace_features(tr, e)
         for i in pick_rounds(st.rounds, per_run, rng):
             Xs.append(X[i])
-            ts.append(rollout(cc, gh, order, tr, i) if label == "rollout" else lookahead(cc, gh, order, tr, i))
+            ts.append(rollout(cc, gh, order, tr, i))
             log(f"  {kind} eps={e}: round {i}/{st.rounds} -> eps* {math.exp(ts[-1]):.3g}")
     return np.array(Xs), np.array(ts)
 
@@ -238,7 +190,6 @@ def main():
     tr.add_argument("--lr", type=float, default=3e-3)
     tr.add_argument("--seed", type=int, default=7)
     tr.add_argument("--out", default=WEIGHTS)
-    tr.add_argument("--label", choices=("rollout", "lookahead"), default="rollout")
     args = ap.parse_args()
 
     import torch
@@ -263,7 +214,7 @@ def main():
     for ps in range(args.passes):
         for name, gh, order, _ in graphs:
             t0 = time.perf_counter()
-            X, t = collect(cc, gh, order, bases if ps == 0 else [], args.per_run, rng, weights, args.label)
+            X, t = collect(cc, gh, order, bases if ps == 0 else [], args.per_run, rng, weights)
             X_all = np.concatenate([X_all, X])
             t_all = np.concatenate([t_all, t])
             log(f"pass {ps} {name}: {len(t)} labelled states in {time.perf_counter() - t0:.1f} s "
@@ -271,8 +222,7 @@ def main():
         weights, loss = train_mlp(cc, X_all, t_all, args.steps, args.lr, args.seed + ps)
         log(f"pass {ps}: trained on {len(t_all)} states, final mse {loss:.4f}")
     save(weights, {"trained_on": [n for n, *_ in graphs], "samples": int(len(t_all)), "mse": loss,
-                   "label": "rollout: fastest fixed eps for the rest of the run" if args.label == "rollout"
-                   else "one-round look-ahead, vertices clustered per microsecond",
+                   "label": "rollout: fastest fixed eps for the rest of the run",
                    "candidates": CANDIDATES}, path=args.out)
     log(f"wrote {args.out}")
 

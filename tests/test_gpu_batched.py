@@ -206,11 +206,31 @@ def test_batch_errors(cc):
     assert ei.value.code == cc.CC_ERR_INVALID_ARG
 
 
-def test_batched_workload_full(cc):
-    """The batched workload at full size: 4096 planted-block graphs."""
+@pytest.fixture(scope="module")
+def sbm4096(cc):
     g = graphgen.workload("sbm4096")
-    gh = upload_batch(cc, g)
-    order = graphgen.batch_permutations(g.vtx_ptr, 4096)
-    parts = split(g)
+    return g, upload_batch(cc, g), split(g), graphgen.batch_permutations(g.vtx_ptr, 4096)
+
+
+# the default shape, then shapes the autotuner picked for this workload
+FULL_SHAPES = [None, (1024, 384, 1792), (1024, 256, 1792), (512, 256, 2048)]
+
+
+@pytest.mark.parametrize("shape", FULL_SHAPES)
+def test_batched_workload_full(cc, sbm4096, shape):
+    """The batched workload at full size: 4096 planted-block graphs, with the
+    default launch shape and the autotuned ones the benchmark runs."""
+    g, gh, parts, order = sbm4096
+    if shape is not None:
+        cc.cc_batch_set_config(gh, *shape)
     for algo in (oracle.C4, oracle.CW):
+        check_batch(cc, algo, g, gh, order, 0.5, parts)
+
+
+def test_batched_workload_autotuned(cc, sbm4096):
+    """Whatever shape the autotuner picks on this device is checked too."""
+    g, gh, parts, order = sbm4096
+    for algo in (oracle.C4, oracle.CW):
+        best = cc.cc_batch_autotune(gh, order, algo, 0.5)
+        assert best.block in (256, 512, 1024) and best.ms > 0
         check_batch(cc, algo, g, gh, order, 0.5, parts)

@@ -4,11 +4,12 @@ the device, fixed rule).
 
 - Chung-Lu power law, n = 2,000,000, gamma = 2.1, mean degree 40 (about 40 M
   positive edges): labels and the whole round trace against the oracle for
-  C4 and ClusterWild! at eps 0.1, 0.5 and 0.9.
-- R-MAT scale 26 (about 1.05 G positive edges), eps = 0.5: C4 labels by the
-  any-size KwikCluster checker (centers independent and maximal in pi order,
-  every vertex on its lowest-rank adjacent center) and ClusterWild! labels and
-  trace against the oracle's round loop.
+  C4 and ClusterWild! at eps 0.1, 0.5 and 0.9 (order 21), and at eps 0.5 for
+  orders 22-25.
+- R-MAT scale 26 (about 1.05 G positive edges), eps = 0.5, orders 31-33:
+  labels, round count and every trace field against the oracle's round loop
+  for C4 and ClusterWild!, C4's labels also by the any-size KwikCluster
+  checker, and the cost.
 """
 import numpy as np
 import pytest
@@ -66,16 +67,44 @@ def test_chunglu_2m(cc, chunglu, algo, eps):
         assert oracle.check_kc(g.off, g.col, order, lab) == (0, -1)
 
 
-@pytest.mark.timeout(900)
-def test_rmat26(cc):
-    g = graphgen.workload("rmat26")
-    gh, _keep, order, dorder = resident(cc, g, 31)
-    lab, st = run(cc, oracle.C4, gh, dorder, 0.5)
-    bad, first = oracle.check_kc(g.off, g.col, order, lab)
-    assert bad == 0, f"C4 on R-MAT 26: {bad} vertices break KwikCluster, first {first}"
-    assert int(cc.cc_cost(gh, lab)[0]) == oracle.cost(g.off, g.col, lab)
-    lab, st = run(cc, oracle.CW, gh, dorder, 0.5)
-    ref = oracle.bsp(oracle.CW, g.off, g.col, order, 0.5)
-    assert_labels_equal(lab, ref.labels, "ClusterWild! on R-MAT 26")
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("seed", [22, 23, 24, 25])
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+def test_chunglu_2m_orders(cc, chunglu, algo, seed):
+    g, gh, _keep, _order, _dorder = chunglu
+    order = graphgen.permutation(g.n, seed)
+    lab, st = run(cc, algo, gh, torch_cuda().from_numpy(order).cuda(), 0.5)
+    ref = oracle.bsp(algo, g.off, g.col, order, 0.5)
+    assert_labels_equal(lab, ref.labels, f"Chung-Lu 2M order {seed}")
     assert st.rounds == ref.rounds
     assert_trace_equal(st.trace, ref.trace, ref.rounds)
+
+
+@pytest.fixture(scope="module")
+def rmat26(cc):
+    torch = torch_cuda()
+    g = graphgen.workload("rmat26")
+    off = torch.from_numpy(np.ascontiguousarray(g.off)).cuda()
+    col = torch.from_numpy(np.ascontiguousarray(g.col)).cuda()
+    gh = cc.cc_graph_from_csr(off, col, borrow=True)
+    return g, gh, (off, col)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("seed", [31, 32, 33])
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+def test_rmat26(cc, rmat26, algo, seed):
+    g, gh, _keep = rmat26
+    order = graphgen.permutation(g.n, seed)
+    name = ("C4" if algo == oracle.C4 else "ClusterWild!") + f" on R-MAT 26, order {seed}"
+    print(f"{name}: GPU run", flush=True)
+    lab, st = run(cc, algo, gh, torch_cuda().from_numpy(order).cuda(), 0.5)
+    print(f"{name}: oracle run", flush=True)
+    ref = oracle.bsp(algo, g.off, g.col, order, 0.5)
+    assert_labels_equal(lab, ref.labels, name)
+    assert st.rounds == ref.rounds
+    assert_trace_equal(st.trace, ref.trace, ref.rounds)
+    if algo == oracle.C4:
+        bad, first = oracle.check_kc(g.off, g.col, order, lab)
+        assert bad == 0, f"{name}: {bad} vertices break KwikCluster, first {first}"
+    assert int(cc.cc_cost(gh, lab)[0]) == oracle.cost(g.off, g.col, ref.labels)

@@ -218,6 +218,93 @@ def test_errors_leave_outputs_untouched(cc):
     assert np.array_equal(lab, oracle.kwikcluster(g.off, g.col, good))
 
 
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+def test_device_outputs_untouched_on_failure(cc, algo):
+    """A failure inside the round loop (forced from the host through the
+    fault_round test hook: every kernel still exits normally) and a bad
+    permutation found on the device both leave a device label buffer as it
+    was; the handle keeps working afterwards."""
+    torch = torch_cuda()
+    g = graphgen.erdos_renyi(20_000, 10.0, seed=6)
+    gh = upload(g)
+    fn = cc.cc_c4 if algo == oracle.C4 else cc.cc_clusterwild
+    order = graphgen.permutation(g.n, 6)
+    dorder = torch.from_numpy(order).cuda()
+    out = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+    for k in (1, 2, 5):
+        with pytest.raises(cc.CCError) as ei:
+            fn(gh, dorder, 0.5, labels=out, fault_round=k)
+        assert ei.value.code == cc.CC_ERR_DEVICE
+        torch.cuda.synchronize()
+        assert bool((out == -7).all())
+    bad = order.copy()
+    bad[10] = bad[11]
+    with pytest.raises(cc.CCError) as ei:
+        fn(gh, torch.from_numpy(bad).cuda(), 0.5, labels=out)
+    assert ei.value.code == cc.CC_ERR_NOT_PERMUTATION
+    torch.cuda.synchronize()
+    assert bool((out == -7).all())
+    lab, st = fn(gh, dorder, 0.5, labels=out)
+    ref = oracle.bsp(algo, g.off, g.col, order, 0.5)
+    assert_labels_equal(out.cpu().numpy(), ref.labels, "after the failed calls")
+    assert st.rounds == ref.rounds
+
+
+# ----------------------------------------- settling the blocked vertices
+
+def _path(n):
+    return graphgen.from_edges(n, [(i, i + 1) for i in range(n - 1)])
+
+
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+def test_blocked_chain_identity_order(cc, algo):
+    """A path with the identity order: round 0's 5000 active vertices form one
+    chain of blocked vertices that settles one link at a time."""
+    g = _path(20_000)
+    gh = upload(g)
+    order = np.arange(g.n, dtype=np.int32)
+    _, st, ref = check_against_oracle(algo, g, gh, order, 0.5)
+    assert ref.trace["conflicts"][0] == ref.trace["b_i"][0] - 1
+
+
+def test_blocked_many_listed_edges(cc):
+    """Half of a dense random graph active at once: about 0.4 M conflict edges,
+    settled from the listed edges."""
+    g = graphgen.erdos_renyi(30_000, 100.0, seed=12)
+    gh = upload(g)
+    order = graphgen.permutation(g.n, 12)
+    sched = np.array([g.n // 2], dtype=np.int64)
+    cc.cc_set_eps_policy(cc.CC_EPS_TRACE, sched)
+    ref = oracle.bsp(oracle.C4, g.off, g.col, order, 0.5, sched=sched)
+    lab, st = run_gpu(oracle.C4, gh, order, 0.5)
+    assert_labels_equal(lab, ref.labels, "C4, half the graph active")
+    assert st.rounds == ref.rounds
+    assert np.array_equal(st.trace["conflicts"], ref.trace["conflicts"])
+    assert np.array_equal(st.trace["centers"], ref.trace["centers"])
+
+
+@pytest.mark.parametrize("case", ["complete1500", "er30k_d100"])
+def test_blocked_too_many_edges_to_list(cc, case):
+    """Every vertex active in round 0 gives more conflict edges than the list
+    holds (max(n, 2^20)): the blocked vertices are settled by row sweeps."""
+    if case == "complete1500":
+        n = 1500
+        g = graphgen.from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+    else:
+        g = graphgen.erdos_renyi(30_000, 100.0, seed=13)
+    assert g.m > max(g.n, 1 << 20)  # conflict edges of an all-active round = m
+    gh = upload(g)
+    order = graphgen.permutation(g.n, 13)
+    sched = np.array([g.n], dtype=np.int64)
+    cc.cc_set_eps_policy(cc.CC_EPS_TRACE, sched)
+    ref = oracle.bsp(oracle.C4, g.off, g.col, order, 0.5, sched=sched)
+    lab, st = run_gpu(oracle.C4, gh, order, 0.5)
+    assert_labels_equal(lab, ref.labels, case)
+    assert st.rounds == ref.rounds == 1
+    assert np.array_equal(st.trace["conflicts"], ref.trace["conflicts"])
+    assert np.array_equal(lab, oracle.kwikcluster(g.off, g.col, order))
+
+
 @pytest.mark.parametrize("validate", [False, True])
 def test_graph_errors(cc, validate):
     off = np.array([0, 1, 2], dtype=np.int64)
