@@ -6,7 +6,8 @@ same resident graph and order: every step of the hot path (delta, active-set
 selection, election, claims, peeling, labels) runs once per algorithm.
 `value` is positive edges clustered per second over the step:
 2 * m / step_time.  Inputs (CSR, order, output buffers) are in HBM before the
-timed region starts.
+timed region starts.  Each call is also bracketed by HIP events on the
+stream its kernels run on (whole call: order check, rounds, labels).
 
 Default workload: R-MAT scale 26, edge factor 16, (a,b,c,d) = (0.57, 0.19,
 0.19, 0.05), symmetrised and deduplicated (~1.05e9 undirected positive
@@ -33,14 +34,27 @@ def make_graph(name):
     return graphgen.workload(name)
 
 
-def algorithmic_bytes(st, n):
-    """Bytes the method itself must move in one call (see the design notes):
-    8 B per adjacency item scanned (4 B column + 4 B neighbour word) in the
-    election, claim, degree-refresh and peel passes, 8 B per atomic
-    read-modify-write, and 32 B per vertex (offsets, order, rank, initial
-    state, final label)."""
-    scanned = st.scanned_elect + st.scanned_claim + st.scanned_delta + st.scanned_peel
-    return 8 * scanned + 8 * st.atomics + 32 * n
+def algorithmic_bytes(st, n, nnz, deg, labels, c4):
+    """Bytes the method must move in one call, counted per unit:
+      8 B per adjacency entry (a 4 B column and a 4 B neighbour word) of
+        E_peel = every entry once (each row is walked when its vertex is
+                 clustered, to take it out of its neighbours' degrees),
+        E_claim = the rows of all centers,
+        E_elect = the rows of all active vertices (C4 only);
+      8 B per atomic read-modify-write; 32 B per vertex (offsets, order, rank,
+      initial state, final label).
+    E_claim comes from the labels (a center is its own label); E_elect adds to
+    it the rows of the active vertices that were not centers, which the
+    library's counters give (listed active rows minus listed center rows).
+    Returns (these bytes, the bytes of the entries the implementation actually
+    read: lazy deletion skips rows with no unclustered neighbour left)."""
+    import numpy as np
+    centers = labels == np.arange(n, dtype=labels.dtype)
+    e_claim = int(deg[centers].sum())
+    e_elect = int(st.scanned_elect) + e_claim - int(st.scanned_claim) if c4 else 0
+    alg = 8 * (nnz + e_claim + e_elect) + 8 * st.atomics + 32 * n
+    read = st.scanned_elect + st.scanned_claim + st.scanned_delta + st.scanned_peel
+    return alg, 8 * read + 8 * st.atomics + 32 * n, {"E_peel": nnz, "E_claim": e_claim, "E_elect": e_elect}
 
 
 def source_hash():
@@ -133,9 +147,11 @@ def bench_batched(cc, torch, steps):
     col = torch.from_numpy(g.col).to(dev)
     gh = cc.cc_graph_from_csr(off, col, vtx_ptr=g.vtx_ptr)
     order = torch.from_numpy(graphgen.batch_permutations(g.vtx_ptr, 4096)).to(dev)
-    lab = torch.empty(g.n, dtype=torch.int32, device=dev)
+    labs = {"c4": torch.empty(g.n, dtype=torch.int32, device=dev),
+            "clusterwild": torch.empty(g.n, dtype=torch.int32, device=dev)}
     out = {"workload": "sbm4096", "graphs": g.ngraphs, "n": g.n, "m": g.m}
     for name, algo, fn in (("c4", cc.CC_ALGO_C4, cc.cc_c4), ("clusterwild", cc.CC_ALGO_CLUSTERWILD, cc.cc_clusterwild)):
+        lab = labs[name]
         t0 = time.perf_counter()
         best = cc.cc_batch_autotune(gh, order, algo, 0.5)
         tune_s = time.perf_counter() - t0
@@ -168,58 +184,100 @@ def bench_batched(cc, torch, steps):
     seq_ms = (time.perf_counter() - t0) * 1e3 * g.ngraphs / len(sample)
     out["sequential_c4_ms_estimate"] = round(seq_ms, 1)
     out["speedup_vs_sequential"] = round(seq_ms / out["c4"]["call_ms"], 1)
+    # the timed launch's labels against the single-graph path on the sampled graphs
+    same = all(torch.equal(labs["c4"][int(g.vtx_ptr[i]):int(g.vtx_ptr[i + 1])], li)
+               for i, (_, _, li) in zip(sample, handles))
+    out["c4_labels_equal_single_graph_calls"] = {"graphs_checked": len(sample), "equal": bool(same)}
     return out
 
 
-def bench_learned(cc, torch, gh, order, lab_ref, fixed_stats, reps):
-    """Learned eps policy against the fixed rule (eps = 0.5) on the same graph."""
+def timed_call(cc, torch, fn, gh, order, eps, lab):
+    """One call bracketed by HIP events on the stream its kernels run on."""
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    _, st = fn(gh, order, eps, labels=lab)
+    e1.record(s)
+    e1.synchronize()
+    return st, e0.elapsed_time(e1)
+
+
+def bench_learned(cc, torch, gh, order, lab_ref, eps_fixed, reps):
+    """The learned eps policy against the fixed rule on the same graph and
+    order: eps = 0.5 and every half-octave candidate eps of the trainer (the
+    best fixed eps in hindsight), for C4 and ClusterWild!."""
     import numpy as np
     from paper_1507_05086_amd import policy
     w, lo, hi = policy.load()
     lab = torch.empty_like(lab_ref)
-    cc.cc_set_eps_policy(cc.CC_EPS_LEARNED, w, lo, hi)
-    try:
-        ks = []
-        for _ in range(reps):
-            _, st = cc.cc_c4(gh, order, 0.5, labels=lab)
-            ks.append(st.loop_ms)
-    finally:
+    out = {"fixed_eps": eps_fixed, "candidates": len(policy.CANDIDATES)}
+    for name, fn in (("c4", cc.cc_c4), ("clusterwild", cc.cc_clusterwild)):
         cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
-    torch.cuda.synchronize()
-    same = bool(torch.equal(lab, lab_ref))
-    fixed_ms = float(np.median([s.loop_ms for s in fixed_stats]))
-    learned_ms = float(np.median(ks))
-    return {"fixed_eps": 0.5, "fixed_ms": round(fixed_ms, 3), "fixed_rounds": fixed_stats[-1].rounds,
-            "learned_ms": round(learned_ms, 3), "learned_rounds": st.rounds,
-            "speedup": round(fixed_ms / learned_ms, 3), "labels_identical": same,
-            "policy_fallback": st.policy_fallback}
+        sweep = {}
+        for e in sorted(set(policy.CANDIDATES) | {eps_fixed}):
+            ts = [timed_call(cc, torch, fn, gh, order, e, lab) for _ in range(reps)]
+            sweep[e] = (min(t for _, t in ts), ts[-1][0].rounds)
+        best = min(sweep, key=lambda e: sweep[e][0])
+        cc.cc_set_eps_policy(cc.CC_EPS_LEARNED, w, lo, hi)
+        try:
+            ts = [timed_call(cc, torch, fn, gh, order, 0.5, lab) for _ in range(reps)]
+        finally:
+            cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+        torch.cuda.synchronize()
+        st = ts[-1][0]
+        learned_ms = min(t for _, t in ts)
+        r = {"fixed_ms": round(sweep[eps_fixed][0], 3), "fixed_rounds": sweep[eps_fixed][1],
+             "best_fixed_eps": round(best, 4), "best_fixed_ms": round(sweep[best][0], 3),
+             "best_fixed_rounds": sweep[best][1],
+             "learned_ms": round(learned_ms, 3), "learned_rounds": st.rounds,
+             "speedup_vs_fixed": round(sweep[eps_fixed][0] / learned_ms, 3),
+             "speedup_vs_best_fixed": round(sweep[best][0] / learned_ms, 3),
+             "policy_fallback": st.policy_fallback,
+             "sweep_ms": {f"{e:.4g}": round(t, 3) for e, (t, _) in sorted(sweep.items())}}
+        if name == "c4":
+            r["labels_identical"] = bool(torch.equal(lab, lab_ref))
+        out[name] = r
+    return out
 
 
-def cpu_baseline(sample):
-    """The oracle, as it stands, on a bounded sample of the same graph family."""
-    import graphgen
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(g, order, eps, gpu_labels):
+    """The oracle as it stands (serial C, one thread) on the benchmarked graph
+    itself: C4's round loop once (ClusterWild! would double the time and
+    says nothing more about the CPU)."""
+    import numpy as np
     import oracle
-    g = graphgen.workload(sample)
-    order = graphgen.permutation(g.n, 31)
     t0 = time.perf_counter()
-    oracle.c4(g.off, g.col, order, 0.5)
-    t1 = time.perf_counter()
-    oracle.clusterwild(g.off, g.col, order, 0.5)
-    t2 = time.perf_counter()
-    return {"value": 2 * g.m / (t2 - t0), "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample} (n={g.n}, m={g.m}), C4 + ClusterWild! BSP oracle, eps=0.5, one thread: "
-                      f"C4 {t1 - t0:.2f} s, ClusterWild! {t2 - t1:.2f} s"}
+    ref = oracle.c4(g.off, g.col, order, eps)
+    t = time.perf_counter() - t0
+    model, ncpu = host_cpu()
+    return {"value": g.m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"the benchmarked graph itself (n={g.n}, m={g.m}), one C4 call of the BSP oracle, eps={eps}, "
+                      f"one thread: {t:.2f} s, {ref.rounds} rounds",
+            "host_cpu": model, "host_nproc": ncpu,
+            "labels_match_gpu": bool(np.array_equal(ref.labels, gpu_labels))}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat26")
     ap.add_argument("--eps", type=float, default=0.5)
     ap.add_argument("--seed", type=int, default=31)
-    ap.add_argument("--cpu-sample", default="rmat23")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and learned-policy lines")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -250,79 +308,84 @@ def main():
         del src, dst
     t = time.perf_counter()
     g = make_graph(args.workload)
-    log(f"graph {args.workload}: n={g.n} m={g.m} max_deg={int(g.degrees().max())} "
+    deg = g.degrees()
+    log(f"graph {args.workload}: n={g.n} m={g.m} max_deg={int(deg.max())} "
         f"generated in {time.perf_counter() - t:.1f} s")
     off = torch.from_numpy(np.ascontiguousarray(g.off)).to(dev)
     col = torch.from_numpy(np.ascontiguousarray(g.col)).to(dev)
-    n, m = g.n, g.m
-    del g
+    n, m, nnz = g.n, g.m, g.nnz
+    torch.cuda.synchronize()
+    t = time.perf_counter()
     gh = cc.cc_graph_from_csr(off, col, borrow=True)
-    order = torch.from_numpy(graphgen.permutation(n, args.seed)).to(dev)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t) * 1e3
+    order_h = graphgen.permutation(n, args.seed)
+    order = torch.from_numpy(order_h).to(dev)
     lab_c4 = torch.empty(n, dtype=torch.int32, device=dev)
     lab_cw = torch.empty(n, dtype=torch.int32, device=dev)
     cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
 
     def step():
-        _, s4 = cc.cc_c4(gh, order, args.eps, labels=lab_c4)
-        _, sw = cc.cc_clusterwild(gh, order, args.eps, labels=lab_cw)
+        s4 = timed_call(cc, torch, cc.cc_c4, gh, order, args.eps, lab_c4)
+        sw = timed_call(cc, torch, cc.cc_clusterwild, gh, order, args.eps, lab_cw)
         return s4, sw
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     stats = []
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record()
     for _ in range(args.steps):
         stats.append(step())
-    ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     value = 2 * m / (ms_per_step / 1e3)
 
-    c4 = [s[0] for s in stats]
-    cw = [s[1] for s in stats]
+    def summary(runs, labels, c4):
+        st = runs[-1][0]
+        call = float(np.median([t for _, t in runs]))
+        loop = float(np.median([r.loop_ms for r, _ in runs]))
+        alg, read, units = algorithmic_bytes(st, n, nnz, deg, labels, c4)
+        return {"call_ms": round(call, 3), "loop_ms": round(loop, 3), "rounds": st.rounds,
+                "edges_per_s": m / (call / 1e3), "alg_bytes": alg, "achieved_gbs": alg / (call / 1e3) / 1e9,
+                "units": units, "read_bytes": read, "read_gbs": read / (call / 1e3) / 1e9,
+                "atomics": st.atomics, "blocked": st.blocked,
+                "scanned": {"elect": st.scanned_elect, "claim": st.scanned_claim,
+                            "delta": st.scanned_delta, "peel": st.scanned_peel}}
 
-    def summary(runs):
-        loop = float(np.mean([r.loop_ms for r in runs]))
-        nbytes = algorithmic_bytes(runs[-1], n)
-        return {"loop_ms": round(loop, 3), "rounds": runs[-1].rounds, "edges_per_s": m / (loop / 1e3),
-                "alg_bytes": nbytes, "achieved_gbs": nbytes / (loop / 1e3) / 1e9,
-                "atomics": runs[-1].atomics,
-                "scanned": {"elect": runs[-1].scanned_elect, "claim": runs[-1].scanned_claim,
-                            "delta": runs[-1].scanned_delta, "peel": runs[-1].scanned_peel}}
-
-    s4, sw = summary(c4), summary(cw)
-    dom = s4 if s4["loop_ms"] >= sw["loop_ms"] else sw
-    dom_name = "cc_c4" if dom is s4 else "cc_clusterwild"
+    lab4_h, labw_h = lab_c4.cpu().numpy(), lab_cw.cpu().numpy()
+    s4 = summary([x[0] for x in stats], lab4_h, True)
+    sw = summary([x[1] for x in stats], labw_h, False)
+    dom_name, dom = ("cc_c4", s4) if s4["call_ms"] >= sw["call_ms"] else ("cc_clusterwild", sw)
     tr = measured_traffic(args.workload)
     traffic = None
     if tr is not None and dom_name in tr.get("calls", {}):
         traffic = tr["calls"][dom_name]["hbm_bytes"]
     roof = {"bound": "hbm", "achieved": round(dom["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "round loop of " + dom_name + " (all kernels of one call)"}
+            "kernel": f"one whole {dom_name} call (order check, every round's kernels, labels): "
+                      f"algorithmic bytes / call time by HIP events on its stream",
+            "read_frac": round(dom["read_gbs"] / HBM_PEAK_GBS, 4)}
     line = {
-        "metric": "edges/sec (C4 + ClusterWild! round loop, fixed eps)",
+        "metric": "edges/sec and rounds, C4 & ClusterWild on 1B-edge R-MAT; learned-\u03b5 vs fixed-\u03b5 time",
         "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "eps": args.eps, "order_seed": args.seed,
                    "step": "cc_c4 + cc_clusterwild"},
+        "setup_ms": round(setup_ms, 1),
         "c4": s4, "clusterwild": sw,
         "roofline": roof,
     }
     if not args.no_extras:
         log("learned eps policy vs fixed ...")
-        line["learned_eps"] = bench_learned(cc, torch, gh, order, lab_c4, c4, 3)
+        line["learned_eps"] = bench_learned(cc, torch, gh, order, lab_c4, args.eps, 2)
         log("batched workload ...")
         line["batched"] = bench_batched(cc, torch, 5)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(g, order_h, args.eps, lab4_h)
     print(json.dumps(line), flush=True)
 
 

@@ -68,6 +68,15 @@ def _load():
     lib.orc_kc_stepwise_cost.restype = i64
     lib.orc_check_kc.argtypes = [i64, vp, vp, vp, vp, vp]
     lib.orc_check_kc.restype = i64
+    u64, f64 = ctypes.c_uint64, ctypes.c_double
+    lib.orc_binomial.argtypes = [u64, u64, i64, f64]
+    lib.orc_binomial.restype = i64
+    lib.orc_halving_period.argtypes = [i64, i64, f64, f64]
+    lib.orc_halving_period.restype = i64
+    lib.orc_binomial_schedule.argtypes = [i64, i64, f64, f64, u64, vp, i64]
+    lib.orc_binomial_schedule.restype = i64
+    lib.orc_bsp_binomial.argtypes = [i32, i64, vp, vp, vp, f64, f64, u64, vp, vp, i64, vp]
+    lib.orc_bsp_binomial.restype = i64
     _lib = lib
     return lib
 
@@ -175,3 +184,48 @@ def check_kc(off, col, order, labels):
     if r < 0:
         raise ValueError(f"orc_check_kc failed ({r})")
     return int(r), int(first.value)
+
+
+# ------------------------------------------- the paper's practical schedule
+
+DEFAULT_DELTA = 0.1  # failure probability in the halving period of Delta-hat (a reading)
+
+
+def binomial(seed: int, stream: int, n: int, p: float) -> int:
+    """One Binomial(n, p) variate from uniform stream `stream` of `seed`."""
+    return int(_load().orc_binomial(seed, stream, n, p))
+
+
+def halving_period(n: int, delta0: int, eps: float, delta: float = DEFAULT_DELTA) -> int:
+    """Rounds between two halvings of Delta-hat."""
+    return int(_load().orc_halving_period(n, delta0, eps, delta))
+
+
+def binomial_schedule(n: int, delta0: int, eps: float, seed: int, delta: float = DEFAULT_DELTA) -> np.ndarray:
+    """B_0, B_1, ...: pi positions taken by each round until none is left."""
+    lib = _load()
+    rounds = lib.orc_binomial_schedule(n, delta0, eps, delta, seed, None, 0)
+    if rounds < 0:
+        raise ValueError(f"orc_binomial_schedule failed ({rounds})")
+    out = np.zeros(max(rounds, 1), dtype=np.int64)
+    lib.orc_binomial_schedule(n, delta0, eps, delta, seed, out.ctypes.data, rounds)
+    return out[:rounds]
+
+
+def bsp_binomial(algo: int, off, col, order, eps: float = 0.5, seed: int = 0, delta: float = DEFAULT_DELTA,
+                 trace_cap: int = 1 << 20, with_round_of: bool = False) -> BSPResult:
+    """C4 or ClusterWild! with Delta-hat and Binomial batches over pi positions."""
+    off, po = _c(off, np.int64)
+    col, pc = _c(col, np.int32)
+    order, pr = _c(order, np.int32)
+    n = len(off) - 1
+    labels = np.empty(n, dtype=np.int32)
+    trace = np.zeros(trace_cap, dtype=[(f, np.int64) for f in TRACE_FIELDS])
+    round_of = np.full(n, -1, dtype=np.int32) if with_round_of else None
+    rounds = _load().orc_bsp_binomial(algo, n, po, pc, pr, eps, delta, seed, labels.ctypes.data,
+                                      trace.ctypes.data, trace_cap,
+                                      round_of.ctypes.data if with_round_of else None)
+    if rounds < 0:
+        raise ValueError(f"orc_bsp_binomial failed ({rounds})")
+    return BSPResult(labels=labels, rounds=int(rounds), trace=trace[:min(rounds, trace_cap)],
+                     round_of=round_of)

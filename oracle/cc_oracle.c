@@ -33,6 +33,7 @@
  *    earlier-ranked active neighbour: the vertices that would wait inside
  *    isCenter (Algorithm 2), counted the same way for both algorithms.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -395,4 +396,313 @@ int64_t orc_check_kc(int64_t n, const int64_t *off, const int32_t *col, const in
   }
   free(rank);
   return bad;
+}
+
+/* =====================================================================
+ * The paper's practical schedule (Implementation Details: "Estimating but
+ * not computing Delta" and "Binomial sampling instead of fixed-size
+ * batches").
+ *
+ * Readings taken here:
+ *  - Delta-hat starts at Delta_0, the largest degree of G, and is halved
+ *    every K = ceil((2/eps) ln(n log2(Delta_0) / delta)) rounds, with
+ *    log2(Delta_0) read as max(log2 Delta_0, 1) and delta the failure
+ *    probability of the high-probability bound (a parameter; the paper gives
+ *    no value).  In round i, Delta-hat = Delta_0 / 2^floor(i/K).
+ *  - Round i draws B_i ~ Binomial(N_i, p_i) with N_i = the pi positions not
+ *    yet passed (the unprocessed suffix: unclustered and already-clustered
+ *    vertices) and p_i = min(1, eps / Delta-hat) (1 when Delta_0 = 0), and
+ *    takes the next B_i positions; the unclustered vertices among them are
+ *    the active set.  B_i = 0 makes an empty round.
+ *  - The loop runs while vertices are unclustered (Algorithm 2's while).
+ *  - Round i's draw uses the uniform variates u_{i,0}, u_{i,1}, ...:
+ *    u_{i,k} = (x >> 11) * 2^-53 with x the output number (i * 2^32 + k) of
+ *    the SplitMix64 stream keyed by the seed (Steele, Lea and Flood, 2014).
+ *  - The Binomial variate: B = N - Binomial(N, 1 - p) when p > 1/2;
+ *    otherwise inversion by sequential search (the BINV algorithm of
+ *    Kachitvichyanukul and Schmeiser, 1988) when N p < 10, and Hormann's
+ *    transformed rejection with decomposition (BTRD, 1993) when N p >= 10.
+ * ===================================================================== */
+
+static uint64_t orc_splitmix(uint64_t key, uint64_t idx) {
+  /* output number idx (from 0) of the SplitMix64 generator seeded with key */
+  uint64_t z = key + (idx + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+typedef struct {
+  uint64_t seed, stream, k;
+} orc_uniforms;
+
+static double orc_uniform(orc_uniforms *g) {
+  const uint64_t x = orc_splitmix(g->seed, (g->stream << 32) + g->k);
+  g->k++;
+  return (double)(x >> 11) * 0x1.0p-53;
+}
+
+/* Inversion: walk the probabilities P(0), P(1), ... (each from the last by
+ * P(x) = P(x-1) (N - x + 1) p / (x q)) until they add up past u. */
+static int64_t orc_binv(int64_t n, double p, orc_uniforms *g) {
+  const double q = 1.0 - p;
+  const double s = p / q;
+  const double a = (double)(n + 1) * s;
+  const double p0 = pow(q, (double)n);
+  for (;;) {
+    double u = orc_uniform(g);
+    double f = p0;
+    int64_t x = 0;
+    while (u > f) {
+      u -= f;
+      x++;
+      if (x > n) break;
+      f *= a / (double)x - s;
+    }
+    if (x <= n) return x;
+  }
+}
+
+/* Stirling-series remainder of log(k!): log k! - [(k+1/2) log(k+1) - (k+1) + log(2 pi)/2]. */
+static double orc_stirling_rest(int64_t k) {
+  if (k <= 9) {
+    const double x = (double)k + 1.0;
+    return lgamma(x) - ((double)k + 0.5) * log(x) + x - 0.5 * log(2.0 * 3.14159265358979323846);
+  }
+  const double x = (double)k + 1.0;
+  const double x2 = x * x;
+  return (1.0 / 12.0 - (1.0 / 360.0 - 1.0 / 1260.0 / x2) / x2) / x;
+}
+
+/* BTRD: a uniform point under a hat built from a transformed uniform is
+ * accepted at once in the hat's central part, else checked against f(k)/f(m)
+ * (m the mode) -- by the product of ratios near the mode, by a squeeze on its
+ * logarithm farther out, and finally by Stirling's formula. */
+static int64_t orc_btrd(int64_t n, double p, orc_uniforms *g) {
+  const double q = 1.0 - p;
+  const double npq = (double)n * p * q;
+  const double spq = sqrt(npq);
+  const double b = 1.15 + 2.53 * spq;
+  const double a = -0.0873 + 0.0248 * b + 0.01 * p;
+  const double c = (double)n * p + 0.5;
+  const double alpha = (2.83 + 5.1 / b) * spq;
+  const double vr = 0.92 - 4.2 / b;
+  const double urvr = 0.86 * vr;
+  const int64_t m = (int64_t)floor((double)(n + 1) * p);
+  const double r = p / q;
+  const double nr = (double)(n + 1) * r;
+  for (;;) {
+    double v = orc_uniform(g);
+    double u;
+    if (v <= urvr) {
+      u = v / vr - 0.43;
+      return (int64_t)floor((2.0 * a / (0.5 - fabs(u)) + b) * u + c);
+    }
+    if (v >= vr) {
+      u = orc_uniform(g) - 0.5;
+    } else {
+      u = v / vr - 0.93;
+      u = (u < 0.0 ? -0.5 : 0.5) - u;
+      v = orc_uniform(g) * vr;
+    }
+    const double us = 0.5 - fabs(u);
+    const double kf = floor((2.0 * a / us + b) * u + c);
+    if (kf < 0.0 || kf > (double)n) continue;
+    const int64_t k = (int64_t)kf;
+    v = v * alpha / (a / (us * us) + b);
+    const int64_t km = k > m ? k - m : m - k;
+    if (km <= 15) {
+      double f = 1.0;
+      if (m < k) {
+        for (int64_t i = m + 1; i <= k; i++) f *= nr / (double)i - r;
+      } else if (m > k) {
+        for (int64_t i = k + 1; i <= m; i++) v *= nr / (double)i - r;
+      }
+      if (v <= f) return k;
+      continue;
+    }
+    v = log(v);
+    const double dkm = (double)km;
+    const double rho = (dkm / npq) * (((dkm / 3.0 + 0.625) * dkm + 1.0 / 6.0) / npq + 0.5);
+    const double t = -dkm * dkm / (2.0 * npq);
+    if (v < t - rho) return k;
+    if (v > t + rho) continue;
+    const double nm = (double)(n - m + 1);
+    const double h = ((double)m + 0.5) * log(((double)m + 1.0) / (r * nm)) + orc_stirling_rest(m) +
+                     orc_stirling_rest(n - m);
+    const double nk = (double)(n - k + 1);
+    if (v <= h + (double)(n + 1) * log(nm / nk) + ((double)k + 0.5) * log(nk * r / ((double)k + 1.0)) -
+                 orc_stirling_rest(k) - orc_stirling_rest(n - k))
+      return k;
+  }
+}
+
+/* One Binomial(n, p) variate from the uniforms of stream `stream`. */
+int64_t orc_binomial(uint64_t seed, uint64_t stream, int64_t n, double p) {
+  orc_uniforms g = {seed, stream, 0};
+  if (n <= 0 || p <= 0.0) return 0;
+  if (p >= 1.0) return n;
+  if (p > 0.5) {
+    const double pc = 1.0 - p;
+    if ((double)n * pc < 10.0) return n - orc_binv(n, pc, &g);
+    return n - orc_btrd(n, pc, &g);
+  }
+  if ((double)n * p < 10.0) return orc_binv(n, p, &g);
+  return orc_btrd(n, p, &g);
+}
+
+/* K: rounds between two halvings of Delta-hat. */
+int64_t orc_halving_period(int64_t n, int64_t delta0, double eps, double delta) {
+  double lg = delta0 > 1 ? log2((double)delta0) : 1.0;
+  if (lg < 1.0) lg = 1.0;
+  const double arg = (double)(n > 1 ? n : 1) * lg / delta;
+  const double k = ceil(2.0 / eps * log(arg));
+  return k < 1.0 ? 1 : (int64_t)k;
+}
+
+/* p_i = min(1, eps / Delta-hat_i), Delta-hat_i = Delta_0 / 2^floor(i/K). */
+static double orc_sample_prob(int64_t round, int64_t period, int64_t delta0, double eps) {
+  if (delta0 <= 0) return 1.0;
+  const int64_t h = round / period;
+  if (h > 1000) return 1.0;
+  const double pr = ldexp(eps / (double)delta0, (int)h);
+  return pr < 1.0 ? pr : 1.0;
+}
+
+/*
+ * The whole position schedule B_0, B_1, ... (it depends on n, Delta_0, eps,
+ * delta and the seed only, never on the graph's state): drawn until the
+ * positions run out.  Writes at most cap entries; returns the number of
+ * rounds the schedule has (which may exceed cap), or a negative code.
+ */
+int64_t orc_binomial_schedule(int64_t n, int64_t delta0, double eps, double delta, uint64_t seed, int64_t *out,
+                              int64_t cap) {
+  if (n < 0 || delta0 < 0 || !(eps > 0.0) || !(delta > 0.0 && delta < 1.0)) return ORC_EINVAL;
+  const int64_t period = orc_halving_period(n, delta0, eps, delta);
+  int64_t left = n, i = 0;
+  while (left > 0) {
+    const int64_t b = orc_binomial(seed, (uint64_t)i, left, orc_sample_prob(i, period, delta0, eps));
+    if (out && i < cap) out[i] = b;
+    left -= b;
+    i++;
+  }
+  return i;
+}
+
+/*
+ * C4 / ClusterWild! with the practical schedule: round i takes the next B_i
+ * positions of pi (drawn as above); the unclustered vertices among them are
+ * the active set; election, claims and peeling as in orc_bsp.  The trace
+ * records n_i, Delta-hat_i (rounded down), B_i (positions), the last
+ * position taken, centers, claimed and blocked vertices.  Returns the number
+ * of rounds or a negative code.
+ */
+int64_t orc_bsp_binomial(int algo, int64_t n, const int64_t *off, const int32_t *col, const int32_t *order,
+                         double eps, double delta, uint64_t seed, int32_t *labels, orc_round *trace,
+                         int64_t trace_cap, int32_t *round_of) {
+  if ((algo != ORC_C4 && algo != ORC_CW) || n < 0) return ORC_EINVAL;
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; v++)
+    if (off[v + 1] - off[v] > maxdeg) maxdeg = off[v + 1] - off[v];
+  const int64_t rounds_max = orc_binomial_schedule(n, maxdeg, eps, delta, seed, NULL, 0);
+  if (rounds_max < 0) return rounds_max;
+  int64_t *sched = malloc(sizeof(int64_t) * (size_t)(rounds_max + 1));
+  int32_t *rank = malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t *best = malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t *active_list = malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t *touched = malloc(sizeof(int32_t) * (size_t)(n + 1));
+  uint8_t *active = calloc((size_t)(n + 1), 1);
+  uint8_t *center = calloc((size_t)(n + 1), 1);
+  int64_t rounds = ORC_ENOMEM;
+  if (!sched || !rank || !best || !active_list || !touched || !active || !center) goto done;
+  orc_binomial_schedule(n, maxdeg, eps, delta, seed, sched, rounds_max + 1);
+  if (orc_invert(n, order, rank) != ORC_OK) {
+    rounds = ORC_EINVAL;
+    goto done;
+  }
+  for (int64_t v = 0; v < n; v++) {
+    labels[v] = ORC_NONE;
+    best[v] = ORC_INF;
+  }
+  const int64_t period = orc_halving_period(n, maxdeg, eps, delta);
+  int64_t n_rem = n, cursor = 0;
+  rounds = 0;
+  while (n_rem > 0) {
+    /* the schedule ends by taking every remaining position, so it lasts */
+    const int64_t b = sched[rounds];
+    const int64_t h = rounds / period;
+    const int64_t dhat = h >= 63 ? 0 : (maxdeg >> h);
+    /* the next b positions; their unclustered vertices are active */
+    int64_t na = 0;
+    for (int64_t k = cursor; k < cursor + b; k++)
+      if (labels[order[k]] == ORC_NONE) active_list[na++] = order[k];
+    cursor += b;
+    for (int64_t i = 0; i < na; i++) active[active_list[i]] = 1;
+    int64_t conflicts = 0;
+    for (int64_t i = 0; i < na; i++) {
+      int32_t a = active_list[i];
+      for (int64_t e = off[a]; e < off[a + 1]; e++)
+        if (active[col[e]] && rank[col[e]] < rank[a]) {
+          conflicts++;
+          break;
+        }
+    }
+    int64_t ncenters = 0;
+    for (int64_t i = 0; i < na; i++) {
+      int32_t a = active_list[i];
+      int ok = 1;
+      if (algo == ORC_C4) {
+        for (int64_t e = off[a]; e < off[a + 1]; e++)
+          if (center[col[e]]) {
+            ok = 0;
+            break;
+          }
+      }
+      center[a] = (uint8_t)ok;
+      ncenters += ok;
+    }
+    int64_t ntouched = 0;
+    for (int64_t i = 0; i < na; i++) {
+      int32_t c = active_list[i];
+      if (!center[c]) continue;
+      for (int64_t e = off[c]; e < off[c + 1]; e++) {
+        int32_t u = col[e];
+        if (labels[u] != ORC_NONE || center[u]) continue;
+        if (algo == ORC_CW && active[u]) continue;
+        if (best[u] == ORC_INF) touched[ntouched++] = u;
+        if (rank[c] < best[u]) best[u] = rank[c];
+      }
+    }
+    for (int64_t i = 0; i < na; i++)
+      if (center[active_list[i]]) labels[active_list[i]] = active_list[i];
+    for (int64_t i = 0; i < ntouched; i++) labels[touched[i]] = order[best[touched[i]]];
+    if (round_of) {
+      for (int64_t i = 0; i < na; i++)
+        if (center[active_list[i]]) round_of[active_list[i]] = (int32_t)rounds;
+      for (int64_t i = 0; i < ntouched; i++) round_of[touched[i]] = (int32_t)rounds;
+    }
+    if (rounds < trace_cap && trace) {
+      orc_round *r = &trace[rounds];
+      r->n_i = n_rem;
+      r->delta_i = dhat;
+      r->b_i = b;
+      r->r_i = cursor - 1;
+      r->centers = ncenters;
+      r->claimed = ntouched;
+      r->conflicts = conflicts;
+    }
+    n_rem -= ncenters + ntouched;
+    for (int64_t i = 0; i < na; i++) active[active_list[i]] = center[active_list[i]] = 0;
+    for (int64_t i = 0; i < ntouched; i++) best[touched[i]] = ORC_INF;
+    rounds++;
+  }
+done:
+  free(sched);
+  free(rank);
+  free(best);
+  free(active_list);
+  free(touched);
+  free(active);
+  free(center);
+  return rounds;
 }
