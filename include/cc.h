@@ -224,8 +224,40 @@ CC_API int32_t cc_cost(const cc_graph *g, const int32_t *labels, int64_t *cost, 
 enum cc_eps_policy_kind {
   CC_EPS_FIXED = 0,   /* the paper's rule with the per-call eps (default) */
   CC_EPS_LEARNED = 1, /* params: 6->64->1 MLP, CC_MLP_PARAMS floats (see below) */
-  CC_EPS_TRACE = 2    /* params: int64 B_i schedule (each >= 1); rounds past its end use the fixed rule */
+  CC_EPS_TRACE = 2,   /* params: int64 B_i schedule (each >= 1); rounds past its end use the fixed rule */
+  CC_EPS_BINOMIAL = 3 /* params: cc_binomial_params; the paper's practical schedule (below) */
 };
+
+/*
+ * The practical schedule of Implementation Details ("Estimating but not
+ * computing Delta", "Binomial sampling instead of fixed-size batches"): no
+ * remaining degree is kept.  Delta-hat starts at Delta_0 (the largest degree)
+ * and halves every K = ceil((2/eps) ln(n max(log2 Delta_0, 1) / delta))
+ * rounds; round i draws B_i ~ Binomial(N_i, min(1, eps / Delta-hat_i)), N_i
+ * the pi positions not yet passed, and its active set is the unclustered
+ * vertices among the next B_i positions (B_i may be 0: an empty round).  C4's
+ * labels are still KwikCluster's.  The B_i sequence depends on (n, Delta_0,
+ * eps, delta, seed) only; the library draws it on the host before the loop
+ * (cc_binomial_schedule shows it).  Round i's variates come from SplitMix64
+ * outputs i*2^32, i*2^32 + 1, ... of `seed`; Binomial(N, p) is N minus a
+ * Binomial(N, 1-p) draw for p > 1/2, inversion (BINV) for N p < 10, else
+ * Hormann's BTRD.  In the trace, delta_i is floor(Delta-hat_i), b_i the
+ * positions taken and r_i the last of them.  Single graphs only.
+ */
+typedef struct cc_binomial_params {
+  uint64_t seed; /* seed of the variates */
+  double delta;  /* failure probability in K, 0 < delta < 1 (the paper gives no value; 0.1 is used here) */
+} cc_binomial_params;
+
+/*
+ * The practical schedule on the host: B_0, B_1, ... until the n positions
+ * are used up.  out (host) receives the first min(capacity, rounds) entries;
+ * *rounds (if not NULL) the schedule's length, *period (if not NULL) K.
+ * CC_ERR_INVALID_ARG for n < 0, delta0 < 0, eps outside (0, 1000] or delta
+ * outside (0, 1).  Touches no device.
+ */
+CC_API int32_t cc_binomial_schedule(int64_t n, int64_t delta0, double eps, uint64_t seed, double delta,
+                                    int64_t *out, int64_t capacity, int64_t *rounds, int64_t *period);
 
 /*
  * Set the process-wide policy (not thread-safe; call between runs).
@@ -235,6 +267,7 @@ enum cc_eps_policy_kind {
  *   per-call eps in round 0); eps_i = clamp(exp(w2 . relu(W1 x + b1) + b2),
  *   eps_min, eps_max); a non-finite output falls back to the fixed rule.
  * TRACE: params = int64[nbytes/8] schedule of B_i.
+ * BINOMIAL: params = one cc_binomial_params (nbytes = its size).
  * FIXED: params ignored.
  */
 CC_API int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes, double eps_min,

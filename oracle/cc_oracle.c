@@ -467,7 +467,7 @@ static int64_t orc_binv(int64_t n, double p, orc_uniforms *g) {
 static double orc_stirling_rest(int64_t k) {
   if (k <= 9) {
     const double x = (double)k + 1.0;
-    return lgamma(x) - ((double)k + 0.5) * log(x) + x - 0.5 * log(2.0 * 3.14159265358979323846);
+    return lgamma(x) - ((double)k + 0.5) * log(x) + x - 0.91893853320467274178; /* log(2 pi) / 2 */
   }
   const double x = (double)k + 1.0;
   const double x2 = x * x;

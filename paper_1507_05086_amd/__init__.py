@@ -39,6 +39,7 @@ CC_OUTPUT_ON_DEVICE = 8
 CC_EPS_FIXED = 0
 CC_EPS_LEARNED = 1
 CC_EPS_TRACE = 2
+CC_EPS_BINOMIAL = 3
 
 CC_MLP_IN, CC_MLP_HIDDEN = 6, 64
 CC_MLP_PARAMS = CC_MLP_HIDDEN * CC_MLP_IN + CC_MLP_HIDDEN + CC_MLP_HIDDEN + 1
@@ -48,7 +49,8 @@ CC_BATCH_MAX_N = 7168
 
 ABI_FUNCTIONS = ("cc_graph_from_csr", "cc_graph_destroy", "cc_graph_info", "cc_c4",
                  "cc_clusterwild", "cc_cost", "cc_batch_set_config", "cc_batch_autotune",
-                 "cc_mlp_forward", "cc_mlp_train_step", "cc_set_eps_policy", "cc_last_error")
+                 "cc_mlp_forward", "cc_mlp_train_step", "cc_set_eps_policy", "cc_binomial_schedule",
+                 "cc_last_error")
 
 TRACE_FIELDS = ("n_i", "delta_i", "b_i", "r_i", "centers", "claimed", "conflicts", "eps_used", "t_ns")
 
@@ -74,6 +76,10 @@ class _RunStats(ctypes.Structure):
                 ("truncated", ctypes.c_int32), ("trace", ctypes.POINTER(_RoundRecord)),
                 ("trace_capacity", ctypes.c_int64), ("graph_rounds", ctypes.POINTER(ctypes.c_int32)),
                 ("max_rounds", ctypes.c_int64), ("fault_round", ctypes.c_int64)]
+
+
+class _BinomialParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("delta", ctypes.c_double)]
 
 
 class _BatchConfig(ctypes.Structure):
@@ -102,6 +108,7 @@ def _load():
         "cc_mlp_forward": ([vp, vp, i64, vp, vp], i32),
         "cc_mlp_train_step": ([vp, vp, vp, vp, vp, i64, i64, ctypes.c_float, vp, vp, vp], i32),
         "cc_set_eps_policy": ([i32, vp, ctypes.c_size_t, f64, f64], i32),
+        "cc_binomial_schedule": ([i64, i64, f64, ctypes.c_uint64, f64, vp, i64, vp, vp], i32),
         "cc_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -326,7 +333,13 @@ def cc_mlp_train_step(params, adam_m, adam_v, x, target, step: int, lr: float, g
 
 
 def cc_set_eps_policy(kind: int, params=None, eps_min: float = 1.0 / 16, eps_max: float = 16.0):
-    """Process-wide epsilon policy: FIXED, LEARNED (float32 MLP weights) or TRACE (int64 schedule)."""
+    """Process-wide epsilon policy: FIXED, LEARNED (float32 MLP weights), TRACE
+    (int64 schedule) or BINOMIAL (params = (seed, delta): the practical schedule)."""
+    if kind == CC_EPS_BINOMIAL:
+        seed, delta = params
+        bp = _BinomialParams(int(seed), float(delta))
+        _check(_lib.cc_set_eps_policy(kind, ctypes.byref(bp), ctypes.sizeof(bp), float(eps_min), float(eps_max)))
+        return
     if kind == CC_EPS_LEARNED:
         a = np.ascontiguousarray(params, dtype=np.float32)
     elif kind == CC_EPS_TRACE:
@@ -336,3 +349,14 @@ def cc_set_eps_policy(kind: int, params=None, eps_min: float = 1.0 / 16, eps_max
     p = ctypes.c_void_p(a.ctypes.data) if a is not None else None
     nbytes = a.nbytes if a is not None else 0
     _check(_lib.cc_set_eps_policy(kind, p, nbytes, float(eps_min), float(eps_max)))
+
+
+def cc_binomial_schedule(n: int, delta0: int, eps: float, seed: int, delta: float = 0.1):
+    """(B_0, B_1, ... as int64, K): the practical schedule the library draws."""
+    rounds, period = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.cc_binomial_schedule(n, delta0, float(eps), int(seed), float(delta), None, 0,
+                                     ctypes.byref(rounds), ctypes.byref(period)))
+    out = np.zeros(max(rounds.value, 1), dtype=np.int64)
+    _check(_lib.cc_binomial_schedule(n, delta0, float(eps), int(seed), float(delta),
+                                     ctypes.c_void_p(out.ctypes.data), rounds.value, None, None))
+    return out[:rounds.value], period.value

@@ -16,6 +16,7 @@
 #include "../../include/cc.h"
 #include "cc_device.h"
 #include "cc_launch.h"
+#include "cc_schedule.h"
 
 using namespace ccd;
 
@@ -46,6 +47,21 @@ struct Policy {
   std::vector<float> mlp;
   std::vector<int64_t> sched;
   double eps_min = 1.0 / 16, eps_max = 16.0;
+  uint64_t bin_seed = 0;   // BINOMIAL
+  double bin_delta = 0.1;  // BINOMIAL
+};
+
+// What the device schedule buffer of a workspace holds (a drawn practical
+// schedule is kept for the next call with the same inputs).
+struct SchedKey {
+  bool binomial = false;
+  int64_t n = 0, delta0 = 0;
+  double eps = 0.0, delta = 0.0;
+  uint64_t seed = 0;
+  bool operator==(const SchedKey &o) const {
+    return binomial == o.binomial && n == o.n && delta0 == o.delta0 && eps == o.eps && delta == o.delta &&
+           seed == o.seed;
+  }
 };
 Policy g_policy;
 std::mutex g_policy_mu;
@@ -86,6 +102,8 @@ struct Workspace {
   int32_t *order_buf = nullptr, *label_buf = nullptr, *iorder = nullptr;
   int64_t *sched = nullptr;
   int64_t sched_cap = 0;
+  SchedKey sched_key;      // the practical schedule the sched buffer holds, if any
+  int64_t sched_len = 0;   // its length
   float *mlp = nullptr;
   int *host_flags = nullptr;  // pinned: done, error, has_round, fallback, phase
   unsigned long long *progress = nullptr;  // pinned, coherent: k_close's progress word
@@ -331,15 +349,34 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
     HIP_TRY(hipMemcpyAsync(ws.order_buf, order, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     d_order = ws.order_buf;
   }
-  if (pol.kind == CC_EPS_TRACE && !pol.sched.empty()) {
-    if ((int64_t)pol.sched.size() > ws.sched_cap) {
+  auto upload_sched = [&](const std::vector<int64_t> &v) -> int32_t {
+    if ((int64_t)v.size() > ws.sched_cap) {
       if (ws.sched) HIP_TRY(hipFree(ws.sched));
       ws.sched = nullptr;
-      HIP_TRY(dalloc(&ws.sched, pol.sched.size()));
-      ws.sched_cap = (int64_t)pol.sched.size();
+      ws.sched_cap = 0;
+      HIP_TRY(dalloc(&ws.sched, v.size()));
+      ws.sched_cap = (int64_t)v.size();
     }
-    HIP_TRY(hipMemcpyAsync(ws.sched, pol.sched.data(), sizeof(int64_t) * pol.sched.size(),
-                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws.sched, v.data(), sizeof(int64_t) * v.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // v is pageable host memory the caller may free
+    return CC_OK;
+  };
+  int64_t bin_period = 1;
+  if (pol.kind == CC_EPS_TRACE && !pol.sched.empty()) {
+    ws.sched_key = SchedKey();
+    if (int32_t rc = upload_sched(pol.sched)) return rc;
+  } else if (pol.kind == CC_EPS_BINOMIAL) {
+    // the practical schedule depends on (n, Delta_0, eps, delta, seed) only
+    SchedKey key{true, n, g->max_deg, eps, pol.bin_delta, pol.bin_seed};
+    bin_period = halving_period(n, g->max_deg, eps, pol.bin_delta);
+    if (!(ws.sched_key == key)) {
+      std::vector<int64_t> bs;
+      binomial_schedule(n, g->max_deg, eps, pol.bin_delta, pol.bin_seed, &bs);
+      ws.sched_key = SchedKey();
+      if (int32_t rc = upload_sched(bs)) return rc;
+      ws.sched_key = key;
+      ws.sched_len = (int64_t)bs.size();
+    }
   }
   if (pol.kind == CC_EPS_LEARNED)
     HIP_TRY(hipMemcpyAsync(ws.mlp, pol.mlp.data(), sizeof(float) * CC_MLP_PARAMS, hipMemcpyHostToDevice, s));
@@ -400,7 +437,8 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.eps = eps;
   w.eps_q = (int64_t)(eps * 1e6 + 0.5);
   w.sched = ws.sched;
-  w.sched_len = pol.kind == CC_EPS_TRACE ? (int64_t)pol.sched.size() : 0;
+  w.sched_len = pol.kind == CC_EPS_TRACE ? (int64_t)pol.sched.size() : pol.kind == CC_EPS_BINOMIAL ? ws.sched_len : 0;
+  w.bin_period = bin_period;
   w.mlp = ws.mlp;
   w.eps_min = (float)pol.eps_min;
   w.eps_max = (float)pol.eps_max;
@@ -827,6 +865,22 @@ extern "C" {
 
 const char *cc_last_error(void) { return g_last_error.c_str(); }
 
+int32_t cc_binomial_schedule(int64_t n, int64_t delta0, double eps, uint64_t seed, double delta, int64_t *out,
+                             int64_t capacity, int64_t *rounds, int64_t *period) {
+  g_last_error.clear();
+  if (n < 0 || delta0 < 0) return fail(CC_ERR_INVALID_ARG, "n and delta0 must be >= 0");
+  if (!(eps > 0.0) || !(eps <= 1000.0) || !std::isfinite(eps)) return fail(CC_ERR_INVALID_ARG, "eps must lie in (0, 1000]");
+  if (!(delta > 0.0 && delta < 1.0)) return fail(CC_ERR_INVALID_ARG, "delta must lie in (0, 1)");
+  if (capacity < 0 || (capacity > 0 && !out)) return fail(CC_ERR_INVALID_ARG, "out is NULL but capacity > 0");
+  std::vector<int64_t> bs;
+  binomial_schedule(n, delta0, eps, delta, seed, &bs);
+  const int64_t k = std::min<int64_t>(capacity, (int64_t)bs.size());
+  if (k > 0) std::memcpy(out, bs.data(), sizeof(int64_t) * (size_t)k);
+  if (rounds) *rounds = (int64_t)bs.size();
+  if (period) *period = halving_period(n, delta0, eps, delta);
+  return CC_OK;
+}
+
 int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_total, const int64_t *offsets,
                           const int32_t *cols, uint32_t flags, void *stream, cc_graph **out) {
   g_last_error.clear();
@@ -1134,6 +1188,13 @@ int32_t cc_set_eps_policy(int32_t kind, const void *params, size_t nbytes, doubl
     p.sched.assign(b, b + nbytes / sizeof(int64_t));
     for (int64_t x : p.sched)
       if (x < 1) return fail(CC_ERR_POLICY, "every scheduled active-set size must be >= 1");
+  } else if (kind == CC_EPS_BINOMIAL) {
+    if (!params || nbytes != sizeof(cc_binomial_params))
+      return fail(CC_ERR_POLICY, "the binomial schedule needs a cc_binomial_params");
+    const cc_binomial_params *bp = (const cc_binomial_params *)params;
+    if (!(bp->delta > 0.0 && bp->delta < 1.0)) return fail(CC_ERR_POLICY, "delta must lie in (0, 1)");
+    p.bin_seed = bp->seed;
+    p.bin_delta = bp->delta;
   } else {
     return fail(CC_ERR_POLICY, "unknown policy kind");
   }

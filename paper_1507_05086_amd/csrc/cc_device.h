@@ -39,7 +39,7 @@ constexpr int HLDS = 256;          // degree-histogram bins kept per workgroup i
 // pass j rescans candidates with bound >= ceil(BAND_j * T_j)
 __host__ __device__ inline float band_factor(int pass) { return pass == 0 ? 0.7f : (pass == 1 ? 0.3f : 0.05f); }
 enum : int { ALGO_C4 = 0, ALGO_CW = 1 };
-enum : int { POL_FIXED = 0, POL_LEARNED = 1, POL_TRACE = 2 };
+enum : int { POL_FIXED = 0, POL_LEARNED = 1, POL_TRACE = 2, POL_BINOMIAL = 3 };
 enum : int { ERR_NONE = 0, ERR_PERM = 5, ERR_NO_PROGRESS = 8, ERR_OVERFLOW = 11, ERR_LABEL = 12, ERR_INJECTED = 13 };
 enum : int { PHASE_LAZY = 0, PHASE_EXACT = 1 };
 
@@ -154,8 +154,9 @@ struct Ws {
   int algo;
   int64_t eps_q;        // per-call eps in millionths
   double eps;
-  const int64_t *sched; // TRACE: B_i schedule (device)
+  const int64_t *sched; // TRACE: B_i schedule; BINOMIAL: pi positions per round (device)
   int64_t sched_len;
+  int64_t bin_period;   // BINOMIAL: rounds between two halvings of Delta-hat
   const float *mlp;     // LEARNED: 6-64-1 weights (device)
   float eps_min, eps_max;
   int64_t max_rounds;   // > 0: stop after this many rounds (partial run)

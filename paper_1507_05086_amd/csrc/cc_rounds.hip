@@ -125,13 +125,24 @@ __device__ inline bool mlp_eps(const Ws &w, const float x[6], float *eps_out) {
   return isfinite(e);
 }
 
+// Delta-hat of round i under the practical schedule: Delta_0 halved every
+// bin_period rounds (rounded down, as the trace records it).
+__device__ inline long long delta_hat(const Ws &w, long long round) {
+  const long long h = round / w.bin_period;
+  return h >= 63 ? 0 : (long long)w.max_deg >> h;
+}
+
 // Sizes the next round; called by all lanes of wave 0 with the same values.
 __device__ void next_batch(const Ws &w, long long n_rem, long long delta, long long round, float fconf,
                            float fclaim, float feps, long long *b_out, double *eps_out, int *fallback) {
   long long b = 0;
   double eps_used = w.eps;
   bool have = false;
-  if (w.policy == POL_TRACE && round < w.sched_len) {
+  if (w.policy == POL_BINOMIAL) {  // round < sched_len: checked by the caller
+    b = w.sched[round];
+    eps_used = w.eps;
+    have = true;
+  } else if (w.policy == POL_TRACE && round < w.sched_len) {
     b = w.sched[round];
     if (b > n_rem) b = n_rem;
     eps_used = delta > 0 ? (double)b * (double)delta / (double)n_rem : 0.0;
@@ -440,6 +451,96 @@ __device__ inline long long lookback(const Ws &w, unsigned t) {
   return excl;
 }
 
+// The positions of this thread's slots marked in `act` hold this round's
+// active vertices (vv[k] at position base + k).  An active vertex with no
+// unclustered neighbour (degree 0, or an exact remaining degree of 0) is a
+// center that claims nobody and that no other active vertex can see: it is
+// settled here and never listed.  Its label stays unset; k_finalize makes it
+// its own center (an isolated vertex once the run is complete -- a partial
+// run labels the isolated vertices it reaches -- or a vertex with its bit
+// cleared and no label).  The others go to the active list with their row
+// info.  Collective: every thread of the workgroup calls it.
+__device__ inline void activate(const Ws &w, Ctrl *c, const int32_t vv[SIPT], unsigned act, int64_t base, bool exact,
+                                int64_t *sh, unsigned long long *s_base) {
+  int64_t wsum = 0;
+  int cnt = 0, lone = 0;
+  unsigned clears = 0;
+  unsigned listed = 0;
+  int32_t wt[SIPT];
+  int64_t rs[SIPT];
+#pragma unroll
+  for (int k = 0; k < SIPT; k++) {
+    wt[k] = 0;
+    rs[k] = 0;
+    if (act & (1u << k)) {
+      const int32_t v = vv[k];
+      if (v >= w.iso_start) {
+        if (w.max_rounds > 0) w.lab[v] = (int32_t)(base + k);  // a partial run must tell it apart
+        lone++;
+      } else if (exact && w.ub[v] == 0) {
+        atomicAnd(&w.unc[v >> 5], ~(1u << (v & 31)));
+        lone++;
+        clears++;
+      } else {
+        rs[k] = w.off[v];
+        wt[k] = (int32_t)(w.off[v + 1] - rs[k]);
+        listed |= 1u << k;
+        cnt++;
+        wsum += wt[k];
+      }
+    }
+  }
+  int64_t wtot, ctot;
+  const int64_t wpre = wg_excl_scan<SEL_BS>(wsum, &wtot, sh);
+  // listed count in the low 32 bits, settled count above (a tile holds < 2^32)
+  const int64_t cpre = wg_excl_scan<SEL_BS>((int64_t)cnt | ((int64_t)lone << 32), &ctot, sh) & 0xFFFFFFFFll;
+  const int64_t ltot = ctot >> 32;
+  ctot &= 0xFFFFFFFFll;
+  if (threadIdx.x == 0 && ctot > 0) *s_base = atomicAdd(&c->a_pack, pk(wtot, ctot));
+  if (threadIdx.x == 0 && ltot > 0) atomicAdd(&c->spread_lone[blockIdx.x & 63], (unsigned long long)ltot);
+  const int64_t wc = wave_sum((int64_t)clears);  // every lane takes part in the sum
+  if (lane_id() == 0 && wc) atomicAdd(&c->spread_atom[blockIdx.x & 63], (unsigned long long)wc);
+  __syncthreads();
+  if (ctot > 0) {
+    int64_t slot = pk_cnt(*s_base) + cpre, wpos = pk_work(*s_base) + wpre;
+#pragma unroll
+    for (int k = 0; k < SIPT; k++) {
+      if (listed & (1u << k)) {
+        const int32_t v = vv[k];
+        w.state[v] = ACTIVE;
+        // the rank of an active vertex, as its neighbours will ask for it:
+        // ClusterWild! keeps it as the label (every active vertex is a center)
+        if (w.algo == ALGO_CW) w.lab[v] = (int32_t)(base + k);
+        else w.rank[v] = (int32_t)(base + k);
+        w.alist[slot] = v;
+        w.awork[slot] = wpos;
+        w.ainfo[slot] = RowInfo{rs[k], wt[k], (int32_t)(base + k)};
+        slot++;
+        wpos += wt[k];
+      }
+    }
+  }
+}
+
+// An unclustered-or-isolated mask of this thread's slots from base on (an
+// isolated vertex's bit is never cleared: only its own position, which the
+// cursor passes once, asks whether it is clustered).
+__device__ inline unsigned load_slots(const Ws &w, int64_t base, int64_t end, int32_t vv[SIPT]) {
+  unsigned un = 0;
+#pragma unroll
+  for (int k = 0; k < SIPT; k++) {
+    const int64_t p = base + k;
+    vv[k] = p < end ? w.order[p] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < SIPT; k++) {
+    const int64_t p = base + k;
+    if (p < end && (vv[k] >= w.iso_start || unc_bit(w.unc, vv[k]))) un |= 1u << k;
+  }
+  return un;
+}
+
+// The next B_i unclustered vertices of pi (Algorithm 2's active set).
 __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
   Ctrl *c = w.ctrl;
   if (c->done) return;
@@ -471,19 +572,7 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     }
     const int64_t base = cur0 + (int64_t)t * TSEL + (int64_t)threadIdx.x * SIPT;
     int32_t vv[SIPT];
-    unsigned un = 0;
-#pragma unroll
-    for (int k = 0; k < SIPT; k++) {
-      const int64_t p = base + k;
-      vv[k] = p < n ? w.order[p] : 0;
-    }
-    // an isolated vertex's bit is never cleared: only its own position,
-    // which the cursor passes once, asks whether it is clustered
-#pragma unroll
-    for (int k = 0; k < SIPT; k++) {
-      const int64_t p = base + k;
-      if (p < n && (vv[k] >= w.iso_start || unc_bit(w.unc, vv[k]))) un |= 1u << k;
-    }
+    const unsigned un = load_slots(w, base, n, vv);
     int64_t agg;
     const int64_t mine = wg_excl_scan<SEL_BS>(__popc(un), &agg, sh);
     if (threadIdx.x < 64) {  // wave 0 publishes and looks back
@@ -499,41 +588,14 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
     }
     __syncthreads();
     const long long excl = s_excl;
-    // the first (B - excl) unclustered positions of this tile are active.  An
-    // active vertex with no unclustered neighbour (degree 0, or an exact
-    // remaining degree of 0) is a center that claims nobody and that no
-    // other active vertex can see: it is settled here and never listed.  Its
-    // label stays unset; k_finalize makes it its own center (an isolated
-    // vertex once the run is complete -- a partial run labels the isolated
-    // vertices it reaches -- or a vertex with its bit cleared and no label).
-    int64_t wsum = 0;
-    int cnt = 0, lone = 0;
-    unsigned clears = 0;
+    // the first (B - excl) unclustered positions of this tile are active
     unsigned act = 0;
-    int32_t wt[SIPT];
-    int64_t rs[SIPT];
     long long r = excl + mine;
 #pragma unroll
     for (int k = 0; k < SIPT; k++) {
-      wt[k] = 0;
-      rs[k] = 0;
       if (un & (1u << k)) {
         if (r < B) {
-          const int32_t v = vv[k];
-          if (v >= w.iso_start) {
-            if (w.max_rounds > 0) w.lab[v] = (int32_t)(base + k);  // a partial run must tell it apart
-            lone++;
-          } else if (exact && w.ub[v] == 0) {
-            atomicAnd(&w.unc[v >> 5], ~(1u << (v & 31)));
-            lone++;
-            clears++;
-          } else {
-            rs[k] = w.off[v];
-            wt[k] = (int32_t)(w.off[v + 1] - rs[k]);
-            act |= 1u << k;
-            cnt++;
-            wsum += wt[k];
-          }
+          act |= 1u << k;
           if (r == B - 1) {
             c->r_last = base + k;
             st_rlx(&c->select_done, 1);
@@ -542,37 +604,27 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
         r++;
       }
     }
-    int64_t wtot, ctot;
-    const int64_t wpre = wg_excl_scan<SEL_BS>(wsum, &wtot, sh);
-    // listed count in the low 32 bits, settled count above (a tile holds < 2^32)
-    const int64_t cpre = wg_excl_scan<SEL_BS>((int64_t)cnt | ((int64_t)lone << 32), &ctot, sh) & 0xFFFFFFFFll;
-    const int64_t ltot = ctot >> 32;
-    ctot &= 0xFFFFFFFFll;
-    if (threadIdx.x == 0 && ctot > 0) s_base = atomicAdd(&c->a_pack, pk(wtot, ctot));
-    if (threadIdx.x == 0 && ltot > 0) atomicAdd(&c->spread_lone[blockIdx.x & 63], (unsigned long long)ltot);
-    const int64_t wc = wave_sum((int64_t)clears);  // every lane takes part in the sum
-    if (lane_id() == 0 && wc) atomicAdd(&c->spread_atom[blockIdx.x & 63], (unsigned long long)wc);
-    __syncthreads();
-    if (ctot > 0) {
-      int64_t slot = pk_cnt(s_base) + cpre, wpos = pk_work(s_base) + wpre;
-#pragma unroll
-      for (int k = 0; k < SIPT; k++) {
-        if (act & (1u << k)) {
-          const int32_t v = vv[k];
-          w.state[v] = ACTIVE;
-          // the rank of an active vertex, as its neighbours will ask for it:
-          // ClusterWild! keeps it as the label (every active vertex is a center)
-          if (w.algo == ALGO_CW) w.lab[v] = (int32_t)(base + k);
-          else w.rank[v] = (int32_t)(base + k);
-          w.alist[slot] = v;
-          w.awork[slot] = wpos;
-          w.ainfo[slot] = RowInfo{rs[k], wt[k], (int32_t)(base + k)};
-          slot++;
-          wpos += wt[k];
-        }
-      }
-    }
+    activate(w, c, vv, act, base, exact, sh, &s_base);
     if (excl + agg >= B) break;
+    __syncthreads();
+  }
+}
+
+// The practical schedule's active set: the unclustered vertices among the
+// next B_i positions of pi (Binomial batches over the unprocessed suffix).
+// No prefix count is needed, so tiles are dealt statically.
+__global__ void __launch_bounds__(SEL_BS) k_select_range(Ws w) {
+  Ctrl *c = w.ctrl;
+  if (c->done) return;
+  __shared__ int64_t sh[SEL_BS / 64 + 1];
+  __shared__ unsigned long long s_base;
+  const int64_t cur0 = c->cursor;
+  const int64_t end = cur0 + c->b < w.n ? cur0 + c->b : w.n;
+  for (int64_t t = blockIdx.x; cur0 + t * TSEL < end; t += gridDim.x) {
+    const int64_t base = cur0 + t * TSEL + (int64_t)threadIdx.x * SIPT;
+    int32_t vv[SIPT];
+    const unsigned un = load_slots(w, base, end, vv);
+    activate(w, c, vv, un, base, false, sh, &s_base);
     __syncthreads();
   }
 }
@@ -1043,16 +1095,17 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
       c->round += 1;
       if (c->round > w.n + 1) set_error(c, ERR_NO_PROGRESS);
       if (w.fault_round > 0 && c->round == w.fault_round) set_error(c, ERR_INJECTED);
-      // Delta_{i+1} (lazy search, or the exact histogram below)
       long long d = 0;
-      if (phase_run == PHASE_LAZY) {
+      if (w.policy == POL_BINOMIAL) {
+        d = delta_hat(w, c->round);  // Delta-hat_{i+1}: no remaining degree is kept
+      } else if (phase_run == PHASE_LAZY) {  // Delta_{i+1} (lazy search, or the exact histogram below)
         const DSearch s = dsearch(c, DITER);
         if (s.switching) c->phase = PHASE_EXACT;
         else d = s.delta;
       }
       c->delta = d;
     } else {
-      c->delta = w.max_deg;  // Delta_0
+      c->delta = w.max_deg;  // Delta_0 (= Delta-hat_0)
     }
     c->has_round = 1;
     c->a_pack = c->c_pack = c->n_pack = c->p_pack = 0;
@@ -1067,6 +1120,12 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
     }
     c->x_pack = 0;
     if (c->n_rem <= 0 || c->error || (w.max_rounds > 0 && c->round >= w.max_rounds)) c->done = 1;
+    // the practical schedule ends by taking every remaining position, so it
+    // cannot run out while vertices are left
+    if (!c->done && w.policy == POL_BINOMIAL && c->round >= w.sched_len) {
+      set_error(c, ERR_NO_PROGRESS);
+      c->done = 1;
+    }
     n_rem = c->n_rem;
     delta = c->delta;
     round = c->round;
@@ -1110,6 +1169,11 @@ __global__ void __launch_bounds__(64) k_close(Ws w) {
     int fb = 0;
     next_batch(w, n_rem, delta, round, fconf, fclaim, feps, &b, &eps_used, &fb);
     if (threadIdx.x == 0) {
+      if (w.policy == POL_BINOMIAL) {  // positions: the last one taken is known now
+        const long long left = w.n - c->cursor;
+        if (b > left) b = left;
+        c->r_last = c->cursor + b - 1;
+      }
       c->b = b;
       c->eps_used = eps_used;
       if (fb) c->fallback = 1;
@@ -1174,7 +1238,9 @@ hipError_t launch_init(const Ws &w, const unsigned *lvl_init_cnt, hipStream_t s)
 }
 
 hipError_t launch_round(const Ws &w, hipStream_t s, const LaunchShape &ls) {
-  hipLaunchKernelGGL(k_select, dim3(ls.select_grid), dim3(SEL_BS), 0, s, w);
+  const bool binomial = w.policy == POL_BINOMIAL;
+  if (binomial) hipLaunchKernelGGL(k_select_range, dim3(ls.select_grid), dim3(SEL_BS), 0, s, w);
+  else hipLaunchKernelGGL(k_select, dim3(ls.select_grid), dim3(SEL_BS), 0, s, w);
   if (w.algo == ALGO_C4) {
     hipLaunchKernelGGL(k_elect, dim3(ls.edge_grid), dim3(BS), 0, s, w);
     hipLaunchKernelGGL(k_classify, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
@@ -1182,7 +1248,9 @@ hipError_t launch_round(const Ws &w, hipStream_t s, const LaunchShape &ls) {
   }
   hipLaunchKernelGGL(k_claim, dim3(ls.edge_grid), dim3(BS), 0, s, w);
   hipLaunchKernelGGL(k_clear, dim3(ls.vertex_grid), dim3(BS), 0, s, w);
-  if (ls.exact_seen) {
+  if (binomial) {
+    // Delta-hat needs no remaining degrees: no peel, no Delta search
+  } else if (ls.exact_seen) {
     // the run has switched to exact degrees for good: no lazy search
     hipLaunchKernelGGL(k_peel, dim3(ls.edge_grid), dim3(BS), 0, s, w);
   } else {

@@ -25,16 +25,16 @@ def upload(g, validate=True, device=True):
     return cc.cc_graph_from_csr(g.off, g.col, vtx_ptr=g.vtx_ptr, validate=validate)
 
 
-def run_gpu(algo, gh, order, eps, device=True):
+def run_gpu(algo, gh, order, eps, device=True, trace_capacity=1 << 16):
     import paper_1507_05086_amd as cc
     fn = cc.cc_c4 if algo == oracle.C4 else cc.cc_clusterwild
     if device:
         torch = torch_cuda()
         o = torch.from_numpy(np.ascontiguousarray(order)).cuda()
-        lab, st = fn(gh, o, eps)
+        lab, st = fn(gh, o, eps, trace_capacity=trace_capacity)
         torch.cuda.synchronize()
         return lab.cpu().numpy(), st
-    lab, st = fn(gh, np.ascontiguousarray(order), eps)
+    lab, st = fn(gh, np.ascontiguousarray(order), eps, trace_capacity=trace_capacity)
     return lab, st
 
 

@@ -45,7 +45,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     import subprocess
     import paper_1507_05086_amd as cc
     structs = {"cc_round_record": cc._RoundRecord, "cc_run_stats": cc._RunStats,
-               "cc_batch_config": cc._BatchConfig}
+               "cc_batch_config": cc._BatchConfig, "cc_binomial_params": cc._BinomialParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cc.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')

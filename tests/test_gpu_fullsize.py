@@ -9,7 +9,9 @@ the device, fixed rule).
 - R-MAT scale 26 (about 1.05 G positive edges), eps = 0.5, orders 31-33:
   labels, round count and every trace field against the oracle's round loop
   for C4 and ClusterWild!, C4's labels also by the any-size KwikCluster
-  checker, and the cost.
+  checker, and the cost; and both algorithms under the paper's practical
+  schedule (Delta-hat halving, Binomial batches over pi positions) against
+  the oracle's loop with the same schedule.
 """
 import numpy as np
 import pytest
@@ -108,3 +110,22 @@ def test_rmat26(cc, rmat26, algo, seed):
         bad, first = oracle.check_kc(g.off, g.col, order, lab)
         assert bad == 0, f"{name}: {bad} vertices break KwikCluster, first {first}"
     assert int(cc.cc_cost(gh, lab)[0]) == oracle.cost(g.off, g.col, ref.labels)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("algo", [oracle.C4, oracle.CW])
+def test_rmat26_practical_schedule(cc, rmat26, algo):
+    g, gh, _keep = rmat26
+    order = graphgen.permutation(g.n, 31)
+    name = ("C4" if algo == oracle.C4 else "ClusterWild!") + " on R-MAT 26, practical schedule"
+    cc.cc_set_eps_policy(cc.CC_EPS_BINOMIAL, (31, 0.1))
+    try:
+        print(f"{name}: GPU run", flush=True)
+        lab, st = run(cc, algo, gh, torch_cuda().from_numpy(order).cuda(), 0.5)
+    finally:
+        cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+    print(f"{name}: oracle run", flush=True)
+    ref = oracle.bsp_binomial(algo, g.off, g.col, order, 0.5, seed=31, delta=0.1)
+    assert_labels_equal(lab, ref.labels, name)
+    assert st.rounds == ref.rounds
+    assert_trace_equal(st.trace, ref.trace, ref.rounds)

@@ -75,3 +75,35 @@ def test_counter_summary(tmp_path, monkeypatch):
     c4, cw = out["calls"]["cc_c4"], out["calls"]["cc_clusterwild"]
     assert c4["dispatches"] == 3 and cw["dispatches"] == 2
     assert math.isclose(c4["fetch_bytes"], 35 * 1024 / 0.5) and math.isclose(cw["write_bytes"], 3 * 2048 / 1.0)
+
+
+def test_library_draws_the_oracles_practical_schedule():
+    """The library's host-side Binomial schedule is the oracle's, draw for
+    draw (both follow the same published steps in IEEE double arithmetic)."""
+    import paper_1507_05086_amd as cc
+    cases = [(20_000, 25, 0.5, 11), (2_000_000, 9000, 0.1, 21), (2_000_000, 9000, 0.9, 22),
+             (67_108_864, 300_000, 0.5, 31), (5000, 1, 0.5, 3), (5000, 0, 0.5, 3), (1, 7, 2.0, 1),
+             (1000, 999, 40.0, 9), (10**9, 10**6, 0.05, 5)]
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        cases.append((int(rng.integers(1, 10**7)), int(rng.integers(0, 10**5)),
+                      float(np.exp(rng.uniform(np.log(0.02), np.log(20.0)))), int(rng.integers(0, 2**63))))
+    for n, d0, eps, seed in cases:
+        for delta in (0.1, 0.01):
+            lib, period = cc.cc_binomial_schedule(n, d0, eps, seed, delta)
+            ref = oracle.binomial_schedule(n, d0, eps, seed, delta)
+            assert period == oracle.halving_period(n, d0, eps, delta)
+            assert np.array_equal(lib, ref), (n, d0, eps, seed, delta)
+
+
+def test_practical_schedule_argument_checks():
+    import pytest
+    import paper_1507_05086_amd as cc
+    for args in ((-1, 5, 0.5, 1, 0.1), (10, -1, 0.5, 1, 0.1), (10, 5, 0.0, 1, 0.1), (10, 5, 0.5, 1, 1.0)):
+        with pytest.raises(cc.CCError) as ei:
+            cc.cc_binomial_schedule(*args)
+        assert ei.value.code == cc.CC_ERR_INVALID_ARG
+    with pytest.raises(cc.CCError) as ei:
+        cc.cc_set_eps_policy(cc.CC_EPS_BINOMIAL, (1, 0.0))
+    assert ei.value.code == cc.CC_ERR_POLICY
+    cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
