@@ -240,6 +240,113 @@ def bench_learned(cc, torch, gh, order, lab_ref, eps_fixed, reps):
     return out
 
 
+def bench_practical(cc, torch, gh, order, lab_ref, eps, reps, seed=31, delta=0.1):
+    """The paper's practical schedule (Delta-hat halving, Binomial batches over
+    pi positions) on the same graph and order as the fixed rule."""
+    lab = torch.empty_like(lab_ref)
+    out = {"seed": seed, "delta": delta, "eps": eps}
+    cc.cc_set_eps_policy(cc.CC_EPS_BINOMIAL, (seed, delta))
+    try:
+        for name, fn in (("c4", cc.cc_c4), ("clusterwild", cc.cc_clusterwild)):
+            ts = [timed_call(cc, torch, fn, gh, order, eps, lab) for _ in range(reps)]
+            st = ts[-1][0]
+            out[name] = {"call_ms": round(min(t for _, t in ts), 3), "loop_ms": round(st.loop_ms, 3),
+                         "rounds": st.rounds, "empty_rounds": int((st.trace["b_i"] == 0).sum())}
+            if name == "c4":
+                out[name]["labels_identical_to_fixed_rule"] = bool(torch.equal(lab, lab_ref))
+    finally:
+        cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+    return out
+
+
+def bench_async(cc, torch, gh, order, lab_ref, n, nnz, deg, reps):
+    """Asynchronous C4 and ClusterWild! (Algorithm 3, no rounds) on the same
+    graph and order: whole-call time, C4's labels against the round loop's,
+    ClusterWild!'s objective against KwikCluster's (C4's)."""
+    import numpy as np
+    lab = torch.empty_like(lab_ref)
+    out = {}
+    kc_cost = int(cc.cc_cost(gh, lab_ref)[0])
+    for name, fn in (("c4", cc.cc_c4_async), ("clusterwild", cc.cc_clusterwild_async)):
+        ts = []
+        for _ in range(reps):
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            _, st = fn(gh, order, labels=lab)
+            e1.record(s)
+            e1.synchronize()
+            ts.append((st, e0.elapsed_time(e1)))
+        st, call = ts[-1][0], min(t for _, t in ts)
+        labels = lab.cpu().numpy()
+        centers = labels == np.arange(n, dtype=labels.dtype)
+        e_claim = int(deg[centers].sum())
+        # per unit as for the round loop; no peel: nothing keeps degrees
+        alg = 8 * (e_claim + (int(st.scanned_elect) if name == "c4" else 0)) + 8 * st.atomics + 32 * n
+        r = {"call_ms": round(call, 3), "kernel_ms": round(st.loop_ms, 3), "edges_per_s": (nnz // 2) / (call / 1e3),
+             "scanned": {"is_center": st.scanned_elect, "claim": st.scanned_claim}, "atomics": st.atomics,
+             "alg_bytes_no_peel": alg, "achieved_gbs": alg / (call / 1e3) / 1e9}
+        if name == "c4":
+            r["labels_identical_to_round_loop"] = bool(torch.equal(lab, lab_ref))
+        else:
+            cw = int(cc.cc_cost(gh, lab)[0])
+            r["cost_over_kwikcluster"] = round(cw / kc_cost, 5) if kc_cost else None
+        out[name] = r
+    return out
+
+
+def experiments(cc, torch, graphs, orders, eps_list):
+    """The paper's experiment types (Experiments: synchronisation rounds,
+    blocked vertices, objective value) on synthetic stand-ins: for each graph,
+    `orders` seeded orders, C4 and ClusterWild! at each eps under the fixed
+    rule (exact Delta) and under the practical schedule: rounds, the share
+    of vertices C4 blocks, and ClusterWild!'s objective relative to
+    KwikCluster's (C4's labels are KwikCluster's)."""
+    import numpy as np
+    import graphgen
+    dev = torch.device("cuda:0")
+    out = {}
+    for name in graphs:
+        t = time.perf_counter()
+        g = graphgen.workload(name)
+        off = torch.from_numpy(np.ascontiguousarray(g.off)).to(dev)
+        col = torch.from_numpy(np.ascontiguousarray(g.col)).to(dev)
+        gh = cc.cc_graph_from_csr(off, col, borrow=True)
+        lab4 = torch.empty(g.n, dtype=torch.int32, device=dev)
+        labw = torch.empty(g.n, dtype=torch.int32, device=dev)
+        log(f"experiments: {name} n={g.n} m={g.m} ready in {time.perf_counter() - t:.1f} s")
+        res = {"n": g.n, "m": g.m, "orders": orders}
+        for sched in ("fixed", "practical"):
+            for eps in eps_list:
+                rows = []
+                for k in range(orders):
+                    seed = 1000 + k
+                    order = torch.from_numpy(graphgen.permutation(g.n, seed)).to(dev)
+                    if sched == "practical":
+                        cc.cc_set_eps_policy(cc.CC_EPS_BINOMIAL, (seed, 0.1))
+                    try:
+                        _, s4 = cc.cc_c4(gh, order, eps, labels=lab4, trace_capacity=0)
+                        _, sw = cc.cc_clusterwild(gh, order, eps, labels=labw, trace_capacity=0)
+                    finally:
+                        cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+                    kc = int(cc.cc_cost(gh, lab4)[0])
+                    cw = int(cc.cc_cost(gh, labw)[0])
+                    rows.append((s4.rounds, sw.rounds, s4.blocked / g.n, cw / kc if kc else 1.0, s4.loop_ms, sw.loop_ms))
+                a = np.array(rows, dtype=float)
+                res[f"{sched}/eps={eps}"] = {
+                    "c4_rounds_mean": round(a[:, 0].mean(), 1), "cw_rounds_mean": round(a[:, 1].mean(), 1),
+                    "c4_blocked_pct_mean": round(100 * a[:, 2].mean(), 4), "c4_blocked_pct_max": round(100 * a[:, 2].max(), 4),
+                    "cw_over_kc_cost_median": round(float(np.median(a[:, 3])), 5),
+                    "cw_over_kc_cost_max": round(a[:, 3].max(), 5),
+                    "c4_loop_ms_median": round(float(np.median(a[:, 4])), 3),
+                    "cw_loop_ms_median": round(float(np.median(a[:, 5])), 3)}
+                log(f"  {name} {sched} eps={eps}: {res[f'{sched}/eps={eps}']}")
+        out[name] = res
+        del gh, off, col, g
+        torch.cuda.empty_cache()
+    return out
+
+
 def host_cpu():
     model = "unknown"
     try:
@@ -284,6 +391,10 @@ def main():
                     help="run one element-wise copy of this many MiB first (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--experiments", default="",
+                    help="comma-separated workloads: print the experiment tables (rounds, blocked share, "
+                         "ClusterWild!/KwikCluster objective over seeded orders) instead of the benchmark line")
+    ap.add_argument("--orders", type=int, default=10, help="orders per graph and eps for --experiments")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, args.workload, args.copy_calibration_mb)
@@ -300,6 +411,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.experiments:
+        tables = experiments(cc, torch, args.experiments.split(","), args.orders, (0.1, 0.5, 0.9))
+        print(json.dumps({"experiments": tables}), flush=True)
+        return
     if args.copy_calibration_mb:
         src = torch.ones(args.copy_calibration_mb * 2 ** 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -379,6 +494,10 @@ def main():
         "roofline": roof,
     }
     if not args.no_extras:
+        log("asynchronous variants ...")
+        line["async"] = bench_async(cc, torch, gh, order, lab_c4, n, nnz, deg, 3)
+        log("practical schedule ...")
+        line["practical_schedule"] = bench_practical(cc, torch, gh, order, lab_c4, args.eps, 3)
         log("learned eps policy vs fixed ...")
         line["learned_eps"] = bench_learned(cc, torch, gh, order, lab_c4, args.eps, 2)
         log("batched workload ...")

@@ -58,7 +58,7 @@ typedef enum cc_status {
   CC_ERR_NOT_PERMUTATION = 5, /* order is not a permutation of 0..n-1 */
   CC_ERR_OUT_OF_MEMORY = 6,   /* device or host allocation failed */
   CC_ERR_DEVICE = 7,          /* a HIP call failed */
-  CC_ERR_NO_PROGRESS = 8,     /* round loop exceeded n+1 rounds or a bounded wait expired */
+  CC_ERR_NO_PROGRESS = 8,     /* round loop exceeded its round limit or a bounded wait expired */
   CC_ERR_POLICY = 9,          /* invalid epsilon-policy parameters or schedule */
   CC_ERR_OUT_OF_RANGE = 10    /* a column index outside 0..n-1 (always checked) */
 } cc_status;
@@ -106,6 +106,9 @@ typedef struct cc_run_stats {
                               graphs): k > 0 makes the device report an error at the end of
                               round k, as a failing round would, so the call returns
                               CC_ERR_DEVICE with every kernel having exited normally */
+  int64_t async_waves;     /* in: asynchronous calls only.  0 fills the device; k > 0 runs
+                              k waves (1: pi strictly in order, 64 positions at a time, which
+                              makes ClusterWild!'s interleaving reproducible) */
 } cc_run_stats;
 
 /*
@@ -163,6 +166,28 @@ CC_API int32_t cc_c4(const cc_graph *g, const int32_t *order, double eps, int32_
  */
 CC_API int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double eps, int32_t *labels,
                        cc_run_stats *stats, uint32_t flags, void *stream);
+
+/*
+ * Asynchronous C4 and ClusterWild! (Algorithm 3 and section "BSP Algorithms
+ * as a Proxy for Asynchronous Algorithms"): the same vertex rules without
+ * rounds or bulk synchronisation, and without eps.  One persistent launch:
+ * waves take the next 64 positions of pi from a shared counter.  C4 makes a
+ * vertex still unclustered when reached a center iff no earlier-ranked
+ * neighbour is one, waiting for earlier neighbours still being decided
+ * (isCenter); its labels equal KwikCluster's, as the round loop's do.
+ * ClusterWild! makes every vertex still unclustered when reached a center,
+ * with no waiting; its labels depend on how the waves interleave (a center
+ * never changes cluster; a claimed vertex joins the lowest-rank center that
+ * claims it).  Single graphs only; order, labels, flags and errors as for
+ * cc_c4.  stats: rounds = 0, scanned_elect = adjacency entries read by
+ * isCenter, scanned_claim = entries read by claims, atomics = claims that
+ * lowered a label, loop_ms = the asynchronous kernel's time; async_waves as
+ * described above; max_rounds and fault_round must be 0.
+ */
+CC_API int32_t cc_c4_async(const cc_graph *g, const int32_t *order, int32_t *labels, cc_run_stats *stats,
+                           uint32_t flags, void *stream);
+CC_API int32_t cc_clusterwild_async(const cc_graph *g, const int32_t *order, int32_t *labels, cc_run_stats *stats,
+                                    uint32_t flags, void *stream);
 
 /*
  * Batches (num_graphs > 1).  cc_c4 and cc_clusterwild cluster every graph of

@@ -77,6 +77,8 @@ def _load():
     lib.orc_binomial_schedule.restype = i64
     lib.orc_bsp_binomial.argtypes = [i32, i64, vp, vp, vp, f64, f64, u64, vp, vp, i64, vp]
     lib.orc_bsp_binomial.restype = i64
+    lib.orc_bsp_positions.argtypes = [i32, i64, vp, vp, vp, vp, i64, i64, i64, vp, vp, i64, vp]
+    lib.orc_bsp_positions.restype = i64
     _lib = lib
     return lib
 
@@ -229,3 +231,19 @@ def bsp_binomial(algo: int, off, col, order, eps: float = 0.5, seed: int = 0, de
         raise ValueError(f"orc_bsp_binomial failed ({rounds})")
     return BSPResult(labels=labels, rounds=int(rounds), trace=trace[:min(rounds, trace_cap)],
                      round_of=round_of)
+
+
+def bsp_positions(algo: int, off, col, order, sched, trace_cap: int = 1 << 20) -> BSPResult:
+    """Rounds taking the next sched[i] positions of pi (must cover all of them)."""
+    off, po = _c(off, np.int64)
+    col, pc = _c(col, np.int32)
+    order, pr = _c(order, np.int32)
+    sched, ps = _c(sched, np.int64)
+    n = len(off) - 1
+    labels = np.empty(n, dtype=np.int32)
+    trace = np.zeros(trace_cap, dtype=[(f, np.int64) for f in TRACE_FIELDS])
+    rounds = _load().orc_bsp_positions(algo, n, po, pc, pr, ps, len(sched), 0, 0, labels.ctypes.data,
+                                       trace.ctypes.data, trace_cap, None)
+    if rounds < 0:
+        raise ValueError(f"orc_bsp_positions failed ({rounds})")
+    return BSPResult(labels=labels, rounds=int(rounds), trace=trace[:min(rounds, trace_cap)])

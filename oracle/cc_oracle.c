@@ -597,16 +597,25 @@ int64_t orc_binomial_schedule(int64_t n, int64_t delta0, double eps, double delt
  * position taken, centers, claimed and blocked vertices.  Returns the number
  * of rounds or a negative code.
  */
-int64_t orc_bsp_binomial(int algo, int64_t n, const int64_t *off, const int32_t *col, const int32_t *order,
-                         double eps, double delta, uint64_t seed, int32_t *labels, orc_round *trace,
-                         int64_t trace_cap, int32_t *round_of) {
-  if ((algo != ORC_C4 && algo != ORC_CW) || n < 0) return ORC_EINVAL;
-  int64_t maxdeg = 0;
-  for (int64_t v = 0; v < n; v++)
-    if (off[v + 1] - off[v] > maxdeg) maxdeg = off[v + 1] - off[v];
-  const int64_t rounds_max = orc_binomial_schedule(n, maxdeg, eps, delta, seed, NULL, 0);
-  if (rounds_max < 0) return rounds_max;
-  int64_t *sched = malloc(sizeof(int64_t) * (size_t)(rounds_max + 1));
+/*
+ * Rounds that take the next sched[i] positions of pi (the unclustered
+ * vertices among them are active); the schedule must cover all n positions.
+ * delta0 and period only fill the trace's delta_i field (delta0 >> (i /
+ * period); pass period <= 0 for zeros).  Used with the Binomial draws below,
+ * and with fixed position batches (64 positions a round is what one
+ * asynchronous wave does when it runs alone).
+ */
+int64_t orc_bsp_positions(int algo, int64_t n, const int64_t *off, const int32_t *col, const int32_t *order,
+                          const int64_t *sched, int64_t sched_len, int64_t delta0, int64_t period, int32_t *labels,
+                          orc_round *trace, int64_t trace_cap, int32_t *round_of) {
+  if ((algo != ORC_C4 && algo != ORC_CW) || n < 0 || sched_len < 0) return ORC_EINVAL;
+  int64_t covered = 0;
+  for (int64_t i = 0; i < sched_len; i++) {
+    if (sched[i] < 0) return ORC_ETRACE;
+    covered += sched[i];
+  }
+  if (covered < n) return ORC_ETRACE;
+  const int64_t maxdeg = delta0;
   int32_t *rank = malloc(sizeof(int32_t) * (size_t)(n + 1));
   int32_t *best = malloc(sizeof(int32_t) * (size_t)(n + 1));
   int32_t *active_list = malloc(sizeof(int32_t) * (size_t)(n + 1));
@@ -614,8 +623,7 @@ int64_t orc_bsp_binomial(int algo, int64_t n, const int64_t *off, const int32_t 
   uint8_t *active = calloc((size_t)(n + 1), 1);
   uint8_t *center = calloc((size_t)(n + 1), 1);
   int64_t rounds = ORC_ENOMEM;
-  if (!sched || !rank || !best || !active_list || !touched || !active || !center) goto done;
-  orc_binomial_schedule(n, maxdeg, eps, delta, seed, sched, rounds_max + 1);
+  if (!rank || !best || !active_list || !touched || !active || !center) goto done;
   if (orc_invert(n, order, rank) != ORC_OK) {
     rounds = ORC_EINVAL;
     goto done;
@@ -624,13 +632,12 @@ int64_t orc_bsp_binomial(int algo, int64_t n, const int64_t *off, const int32_t 
     labels[v] = ORC_NONE;
     best[v] = ORC_INF;
   }
-  const int64_t period = orc_halving_period(n, maxdeg, eps, delta);
   int64_t n_rem = n, cursor = 0;
   rounds = 0;
   while (n_rem > 0) {
-    /* the schedule ends by taking every remaining position, so it lasts */
-    const int64_t b = sched[rounds];
-    const int64_t h = rounds / period;
+    /* the schedule covers every position, so it lasts */
+    const int64_t b = sched[rounds] < n - cursor ? sched[rounds] : n - cursor;
+    const int64_t h = period > 0 ? rounds / period : 63;
     const int64_t dhat = h >= 63 ? 0 : (maxdeg >> h);
     /* the next b positions; their unclustered vertices are active */
     int64_t na = 0;
@@ -697,12 +704,30 @@ int64_t orc_bsp_binomial(int algo, int64_t n, const int64_t *off, const int32_t 
     rounds++;
   }
 done:
-  free(sched);
   free(rank);
   free(best);
   free(active_list);
   free(touched);
   free(active);
   free(center);
+  return rounds;
+}
+
+int64_t orc_bsp_binomial(int algo, int64_t n, const int64_t *off, const int32_t *col, const int32_t *order,
+                         double eps, double delta, uint64_t seed, int32_t *labels, orc_round *trace,
+                         int64_t trace_cap, int32_t *round_of) {
+  if ((algo != ORC_C4 && algo != ORC_CW) || n < 0) return ORC_EINVAL;
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; v++)
+    if (off[v + 1] - off[v] > maxdeg) maxdeg = off[v + 1] - off[v];
+  const int64_t len = orc_binomial_schedule(n, maxdeg, eps, delta, seed, NULL, 0);
+  if (len < 0) return len;
+  int64_t *sched = malloc(sizeof(int64_t) * (size_t)(len + 1));
+  if (!sched) return ORC_ENOMEM;
+  orc_binomial_schedule(n, maxdeg, eps, delta, seed, sched, len + 1);
+  const int64_t rounds = orc_bsp_positions(algo, n, off, col, order, sched, len, maxdeg,
+                                           orc_halving_period(n, maxdeg, eps, delta), labels, trace, trace_cap,
+                                           round_of);
+  free(sched);
   return rounds;
 }

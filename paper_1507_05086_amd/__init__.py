@@ -48,7 +48,7 @@ CC_ALGO_C4, CC_ALGO_CLUSTERWILD = 0, 1
 CC_BATCH_MAX_N = 7168
 
 ABI_FUNCTIONS = ("cc_graph_from_csr", "cc_graph_destroy", "cc_graph_info", "cc_c4",
-                 "cc_clusterwild", "cc_cost", "cc_batch_set_config", "cc_batch_autotune",
+                 "cc_clusterwild", "cc_c4_async", "cc_clusterwild_async", "cc_cost", "cc_batch_set_config", "cc_batch_autotune",
                  "cc_mlp_forward", "cc_mlp_train_step", "cc_set_eps_policy", "cc_binomial_schedule",
                  "cc_last_error")
 
@@ -75,7 +75,8 @@ class _RunStats(ctypes.Structure):
                 ("loop_ms", ctypes.c_double), ("policy_fallback", ctypes.c_int32),
                 ("truncated", ctypes.c_int32), ("trace", ctypes.POINTER(_RoundRecord)),
                 ("trace_capacity", ctypes.c_int64), ("graph_rounds", ctypes.POINTER(ctypes.c_int32)),
-                ("max_rounds", ctypes.c_int64), ("fault_round", ctypes.c_int64)]
+                ("max_rounds", ctypes.c_int64), ("fault_round", ctypes.c_int64),
+                ("async_waves", ctypes.c_int64)]
 
 
 class _BinomialParams(ctypes.Structure):
@@ -102,6 +103,8 @@ def _load():
         "cc_graph_info": ([vp, vp, vp, vp], i32),
         "cc_c4": ([vp, vp, f64, vp, ctypes.POINTER(_RunStats), u32, vp], i32),
         "cc_clusterwild": ([vp, vp, f64, vp, ctypes.POINTER(_RunStats), u32, vp], i32),
+        "cc_c4_async": ([vp, vp, vp, ctypes.POINTER(_RunStats), u32, vp], i32),
+        "cc_clusterwild_async": ([vp, vp, vp, ctypes.POINTER(_RunStats), u32, vp], i32),
         "cc_cost": ([vp, vp, vp, u32, vp], i32),
         "cc_batch_set_config": ([vp, ctypes.POINTER(_BatchConfig)], i32),
         "cc_batch_autotune": ([vp, i32, vp, f64, u32, vp, ctypes.POINTER(_BatchConfig)], i32),
@@ -269,6 +272,33 @@ def cc_clusterwild(graph: Graph, order, eps: float = 0.5, labels=None, trace_cap
                    stream=None, max_rounds: int = 0, fault_round: int = 0):
     """ClusterWild!.  Returns (labels, RunStats)."""
     return _run(_lib.cc_clusterwild, graph, order, eps, labels, trace_capacity, stream, max_rounds, fault_round)
+
+
+def _run_async(fn, graph: Graph, order, labels=None, waves=0, stream=None):
+    po, odev, _ko = _ptr(order, np.int32)
+    if labels is None:
+        if odev:
+            import torch
+            labels = torch.empty(graph.n, dtype=torch.int32, device=order.device)
+        else:
+            labels = np.empty(graph.n, dtype=np.int32)
+    pl, ldev, _kl = _ptr(labels, np.int32)
+    flags = (CC_INPUT_ON_DEVICE if odev else 0) | (CC_OUTPUT_ON_DEVICE if ldev else 0)
+    st = _RunStats()
+    st.async_waves = int(waves)
+    _check(fn(graph.handle, po, pl, ctypes.byref(st), flags, _stream(stream, order, labels)))
+    return labels, RunStats(scanned_elect=st.scanned_elect, scanned_claim=st.scanned_claim, atomics=st.atomics,
+                            loop_ms=st.loop_ms)
+
+
+def cc_c4_async(graph: Graph, order, labels=None, waves: int = 0, stream=None):
+    """Asynchronous C4 (Algorithm 3): KwikCluster's labels, no rounds.  Returns (labels, RunStats)."""
+    return _run_async(_lib.cc_c4_async, graph, order, labels, waves, stream)
+
+
+def cc_clusterwild_async(graph: Graph, order, labels=None, waves: int = 0, stream=None):
+    """Asynchronous ClusterWild! (Algorithm 3); waves=1 makes the interleaving reproducible."""
+    return _run_async(_lib.cc_clusterwild_async, graph, order, labels, waves, stream)
 
 
 def cc_cost(graph: Graph, labels, stream=None) -> np.ndarray:

@@ -460,6 +460,9 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
 
   LaunchShape ls{512, 1024, 512, 0, 0};
   int64_t launched = 0;
+  // the fixed rule clusters a vertex every round; the practical schedule's
+  // rounds may be empty, and it has as many as it drew
+  const int64_t round_limit = pol.kind == CC_EPS_BINOMIAL ? std::max<int64_t>(n, w.sched_len) : n;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   HIP_TRY(hipEventCreate(&ev0));
   HIP_TRY(hipEventCreate(&ev1));
@@ -504,9 +507,9 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
       std::this_thread::yield();
     }
     if (done) break;
-    if (launched > n + 2) {
+    if (launched > round_limit + 4 * kRoundGroup) {  // a backstop: the device stops a runaway loop itself
       (void)hipStreamSynchronize(s);
-      return fail(CC_ERR_NO_PROGRESS, "round loop exceeded n+1 rounds");
+      return fail(CC_ERR_NO_PROGRESS, "round loop exceeded its round limit");
     }
   }
   HIP_TRY(hipEventRecord(ev1, s));
@@ -564,6 +567,80 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
         o.t_ns = (int64_t)((double)r.t_ns * 1e6 / (double)khz);
       }
     }
+  }
+  return CC_OK;
+}
+
+// ------------------------------------------------------- asynchronous runs
+
+int32_t run_async(cc_graph *g, int algo, const int32_t *order, int32_t *labels, cc_run_stats *stats, uint32_t flags,
+                  hipStream_t s) {
+  if (!g) return fail(CC_ERR_INVALID_ARG, "graph handle is NULL");
+  if (!order || !labels) return fail(CC_ERR_INVALID_ARG, "order and labels must not be NULL");
+  if (flags & ~(uint32_t)(CC_INPUT_ON_DEVICE | CC_OUTPUT_ON_DEVICE))
+    return fail(CC_ERR_INVALID_ARG, "unknown flag for a run");
+  if (g->num_graphs != 1) return fail(CC_ERR_INVALID_ARG, "the asynchronous variants take single graphs");
+  if (stats && (stats->max_rounds != 0 || stats->fault_round != 0))
+    return fail(CC_ERR_INVALID_ARG, "max_rounds and fault_round apply to the round loop only");
+  if (stats && (stats->async_waves < 0 || stats->async_waves > (1 << 20)))
+    return fail(CC_ERR_INVALID_ARG, "stats->async_waves must lie in [0, 2^20]");
+  if (int32_t rc = ensure_ws(g)) return rc;
+  Workspace &ws = g->ws;
+  const int64_t n = g->n;
+  if (n == 0) {
+    if (stats) std::memset(stats, 0, offsetof(cc_run_stats, trace));
+    return CC_OK;
+  }
+  const int32_t *d_order = order;
+  if (!(flags & CC_INPUT_ON_DEVICE)) {
+    HIP_TRY(hipMemcpyAsync(ws.order_buf, order, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    d_order = ws.order_buf;
+  }
+  HIP_TRY(hipMemsetAsync(ws.ctrl, 0, sizeof(Ctrl), s));
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  HIP_TRY(hipEventCreate(&ev0));
+  HIP_TRY(hipEventCreate(&ev1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{ev0, ev1};
+  // the long-row claim list borrows two vertex lists of the round loop
+  AsyncArgs a{g->roff, g->rcol, n, g->iso_start, ws.iorder, ws.rank, ws.lab, ws.ctrl, ws.xlist, ws.plist, n};
+  // labels reach the caller only on success
+  HIP_TRY(launch_async(a, algo, d_order, g->perm, ws.iorder, ws.label_buf, stats ? (int)stats->async_waves : 0, s,
+                       ev0, ev1));
+  Ctrl hc;
+  HIP_TRY(hipMemcpyAsync(&hc, ws.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hc.error == ERR_PERM) return fail(CC_ERR_NOT_PERMUTATION, "order is not a permutation of 0..n-1");
+  if (hc.error == ERR_NO_PROGRESS) return fail(CC_ERR_NO_PROGRESS, "a bounded wait for an earlier vertex expired");
+  if (hc.error) return fail(CC_ERR_DEVICE, "device error " + std::to_string(hc.error) + " in the asynchronous run");
+  HIP_TRY(hipMemcpyAsync(labels, ws.label_buf, sizeof(int32_t) * (size_t)n,
+                         (flags & CC_OUTPUT_ON_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (stats) {
+    unsigned long long walked = 0, claimed = 0, atoms = 0;
+    for (int i = 0; i < 64; i++) {
+      walked += hc.spread_lone[i];
+      claimed += hc.x_low[i];
+      atoms += hc.spread_atom[i];
+    }
+    stats->rounds = 0;
+    stats->scanned_elect = (int64_t)walked;
+    stats->scanned_claim = (int64_t)claimed;
+    stats->scanned_peel = 0;
+    stats->scanned_delta = 0;
+    stats->blocked = 0;
+    stats->atomics = (int64_t)atoms;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+    stats->loop_ms = ms;
+    stats->policy_fallback = 0;
+    stats->truncated = 0;
+    if (stats->graph_rounds) stats->graph_rounds[0] = 0;
   }
   return CC_OK;
 }
@@ -1075,6 +1152,18 @@ int32_t cc_clusterwild(const cc_graph *g, const int32_t *order, double eps, int3
                        cc_run_stats *stats, uint32_t flags, void *stream) {
   g_last_error.clear();
   return run_loop(const_cast<cc_graph *>(g), ALGO_CW, order, eps, labels, stats, flags, (hipStream_t)stream);
+}
+
+int32_t cc_c4_async(const cc_graph *g, const int32_t *order, int32_t *labels, cc_run_stats *stats, uint32_t flags,
+                    void *stream) {
+  g_last_error.clear();
+  return run_async(const_cast<cc_graph *>(g), ALGO_C4, order, labels, stats, flags, (hipStream_t)stream);
+}
+
+int32_t cc_clusterwild_async(const cc_graph *g, const int32_t *order, int32_t *labels, cc_run_stats *stats,
+                             uint32_t flags, void *stream) {
+  g_last_error.clear();
+  return run_async(const_cast<cc_graph *>(g), ALGO_CW, order, labels, stats, flags, (hipStream_t)stream);
 }
 
 int32_t cc_cost(const cc_graph *gc, const int32_t *labels, int64_t *cost, uint32_t flags, void *stream) {

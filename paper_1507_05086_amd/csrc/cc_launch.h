@@ -65,6 +65,27 @@ hipError_t launch_relabel(const int64_t *off, const int32_t *col, const int64_t 
                           int64_t *blocksum, int32_t *rcol, int64_t *first_low, int64_t *first_isolated,
                           hipStream_t s);
 
+// Asynchronous C4 / ClusterWild! (Algorithm 3): one persistent launch, no
+// rounds.  rank and lab are workspace arrays of n; order is pi in internal
+// ids (written by the launch from order_in through perm into iorder).
+struct AsyncArgs {
+  const int64_t *off;
+  const int32_t *col;
+  int64_t n;
+  int64_t iso_start;
+  const int32_t *order;
+  int32_t *rank;
+  int32_t *lab;
+  Ctrl *ctrl;
+  int32_t *big_v, *big_p;  // C4 centers whose claims are spread over the device (vertex, rank)
+  int64_t big_cap;
+};
+// waves > 0 limits the launch to that many waves (1: pi strictly in order,
+// 64 positions at a time); 0 fills the device.  ev0 / ev1 (optional) bracket
+// the asynchronous kernel itself.
+hipError_t launch_async(const AsyncArgs &a, int algo, const int32_t *order_in, const int32_t *perm, int32_t *iorder,
+                        int32_t *labels, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+
 // Learned-policy network: inference over a batch, one training step.
 int mlp_grad_blocks(int n);
 hipError_t launch_mlp_forward(const float *p, const float *x, int n, float *y, hipStream_t s);

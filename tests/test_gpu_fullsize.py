@@ -129,3 +129,29 @@ def test_rmat26_practical_schedule(cc, rmat26, algo):
     assert_labels_equal(lab, ref.labels, name)
     assert st.rounds == ref.rounds
     assert_trace_equal(st.trace, ref.trace, ref.rounds)
+
+
+@pytest.mark.timeout(600)
+def test_rmat26_async(cc, rmat26):
+    """Asynchronous C4 gives KwikCluster's labels on R-MAT 26; asynchronous
+    ClusterWild! gives a clustering whose every label is a center."""
+    torch = torch_cuda()
+    g, gh, _keep = rmat26
+    order = graphgen.permutation(g.n, 31)
+    dorder = torch.from_numpy(order).cuda()
+    print("async C4 on R-MAT 26: GPU run", flush=True)
+    lab, st = cc.cc_c4_async(gh, dorder)
+    torch.cuda.synchronize()
+    lab = lab.cpu().numpy()
+    print(f"  {st.loop_ms:.2f} ms; KwikCluster on the CPU", flush=True)
+    assert_labels_equal(lab, oracle.kwikcluster(g.off, g.col, order), "async C4 on R-MAT 26")
+    kc_cost = oracle.cost(g.off, g.col, lab)
+    print("async ClusterWild! on R-MAT 26: GPU run", flush=True)
+    labw, stw = cc.cc_clusterwild_async(gh, dorder)
+    torch.cuda.synchronize()
+    labw = labw.cpu().numpy()
+    assert ((labw >= 0) & (labw < g.n)).all() and (labw[labw] == labw).all()
+    cw_cost = int(cc.cc_cost(gh, labw)[0])
+    assert cw_cost == oracle.cost(g.off, g.col, labw)
+    print(f"  {stw.loop_ms:.2f} ms; cost {cw_cost} vs KwikCluster {kc_cost}", flush=True)
+    assert cw_cost < 1.5 * kc_cost

@@ -158,3 +158,20 @@ def test_binomial_degenerate_graphs():
             assert ((r.labels >= 0) & (r.labels < n)).all()
             if not edges:
                 assert r.rounds == 1 and r.labels.tolist() == list(range(n))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_position_batches_reduce_to_kwikcluster(seed):
+    """Rounds of fixed position batches: one position a round is KwikCluster
+    for both algorithms; C4 is KwikCluster for any batch size."""
+    g = graphgen.chung_lu(3000, 2.1, 10.0, seed=80 + seed)
+    order = graphgen.permutation(g.n, 80 + seed)
+    kc = oracle.kwikcluster(g.off, g.col, order)
+    ones = np.ones(g.n, dtype=np.int64)
+    for algo in (oracle.C4, oracle.CW):
+        assert np.array_equal(oracle.bsp_positions(algo, g.off, g.col, order, ones).labels, kc)
+    for b in (2, 64, 1000):
+        sched = np.full(-(-g.n // b), b, dtype=np.int64)
+        assert np.array_equal(oracle.bsp_positions(oracle.C4, g.off, g.col, order, sched).labels, kc)
+    with pytest.raises(ValueError):
+        oracle.bsp_positions(oracle.CW, g.off, g.col, order, np.array([g.n - 1], np.int64))
