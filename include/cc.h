@@ -325,6 +325,21 @@ CC_API int32_t cc_mlp_forward(const float *params, const float *x, int64_t n, fl
 CC_API int32_t cc_mlp_train_step(float *params, float *adam_m, float *adam_v, const float *x, const float *target,
                                  int64_t n, int64_t step, float lr, float *grad, float *loss, void *stream);
 
+/*
+ * cc_mlp_train_step without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * cc_mlp_train_step; the partial gradient rows (one per workgroup of the
+ * gradient kernel, at most 1024, about 2 MB) live in a static device buffer
+ * that each device holds until the process ends.  Calls that overlap on one
+ * device share that buffer and race: serialise them.  CC_ERR_INVALID_ARG if
+ * a gradient would need more partial rows than the buffer holds (it never
+ * does: the kernel uses at most 1024 workgroups).
+ */
+CC_API int32_t cc_mlp_train_step_noalloc(float *params, float *adam_m, float *adam_v, const float *x,
+                                         const float *target, int64_t n, int64_t step, float lr, float *grad,
+                                         float *loss, void *stream);
+
 /* Text of the calling thread's last failure ("" if none). */
 CC_API const char *cc_last_error(void);
 

@@ -49,7 +49,8 @@ CC_BATCH_MAX_N = 7168
 
 ABI_FUNCTIONS = ("cc_graph_from_csr", "cc_graph_destroy", "cc_graph_info", "cc_c4",
                  "cc_clusterwild", "cc_c4_async", "cc_clusterwild_async", "cc_cost", "cc_batch_set_config", "cc_batch_autotune",
-                 "cc_mlp_forward", "cc_mlp_train_step", "cc_set_eps_policy", "cc_binomial_schedule",
+                 "cc_mlp_forward", "cc_mlp_train_step", "cc_mlp_train_step_noalloc", "cc_set_eps_policy",
+                 "cc_binomial_schedule",
                  "cc_last_error")
 
 TRACE_FIELDS = ("n_i", "delta_i", "b_i", "r_i", "centers", "claimed", "conflicts", "eps_used", "t_ns")
@@ -110,6 +111,7 @@ def _load():
         "cc_batch_autotune": ([vp, i32, vp, f64, u32, vp, ctypes.POINTER(_BatchConfig)], i32),
         "cc_mlp_forward": ([vp, vp, i64, vp, vp], i32),
         "cc_mlp_train_step": ([vp, vp, vp, vp, vp, i64, i64, ctypes.c_float, vp, vp, vp], i32),
+        "cc_mlp_train_step_noalloc": ([vp, vp, vp, vp, vp, i64, i64, ctypes.c_float, vp, vp, vp], i32),
         "cc_set_eps_policy": ([i32, vp, ctypes.c_size_t, f64, f64], i32),
         "cc_binomial_schedule": ([i64, i64, f64, ctypes.c_uint64, f64, vp, i64, vp, vp], i32),
         "cc_last_error": ([], ctypes.c_char_p),
@@ -360,6 +362,15 @@ def cc_mlp_train_step(params, adam_m, adam_v, x, target, step: int, lr: float, g
     _check(_lib.cc_mlp_train_step(_dev(params, "params"), _dev(adam_m, "adam_m"), _dev(adam_v, "adam_v"),
                                   _dev(x, "x"), _dev(target, "target"), n, int(step), float(lr),
                                   _dev(grad, "grad"), _dev(loss, "loss"), _stream(stream, x)))
+
+
+def cc_mlp_train_step_noalloc(params, adam_m, adam_v, x, target, step: int, lr: float, grad=None, loss=None,
+                              stream=None):
+    """cc_mlp_train_step with the library's static device buffer: allocates nothing."""
+    n = x.shape[0]
+    _check(_lib.cc_mlp_train_step_noalloc(_dev(params, "params"), _dev(adam_m, "adam_m"), _dev(adam_v, "adam_v"),
+                                          _dev(x, "x"), _dev(target, "target"), n, int(step), float(lr),
+                                          _dev(grad, "grad"), _dev(loss, "loss"), _stream(stream, x)))
 
 
 def cc_set_eps_policy(kind: int, params=None, eps_min: float = 1.0 / 16, eps_max: float = 16.0):

@@ -1237,19 +1237,37 @@ int32_t cc_mlp_train_step(float *params, float *adam_m, float *adam_v, const flo
     return fail(CC_ERR_INVALID_ARG, "an Adam step needs adam_m, adam_v and step >= 1");
   hipStream_t s = (hipStream_t)stream;
   const int nblk = mlp_grad_blocks((int)n);
-  // partial gradient rows, one per workgroup; kept for later calls
+  // partial gradient rows, one per workgroup; one buffer per device, kept for later calls
   static std::mutex mu;
-  static float *partial = nullptr;
-  static int cap = 0;
+  static std::map<int, float *> partial;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(mu);
-  if (nblk > cap) {
-    if (partial) HIP_TRY(hipFree(partial));
-    partial = nullptr;
-    cap = 0;
-    HIP_TRY(dalloc(&partial, (size_t)1024 * 514));
-    cap = 1024;
-  }
-  HIP_TRY(launch_mlp_train_step(params, adam_m, adam_v, x, target, (int)n, (long long)step, lr, partial, nblk, grad,
+  float *&rows = partial[dev];
+  if (!rows) HIP_TRY(dalloc(&rows, (size_t)1024 * 514));
+  HIP_TRY(launch_mlp_train_step(params, adam_m, adam_v, x, target, (int)n, (long long)step, lr, rows, nblk, grad,
+                                loss, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return CC_OK;
+}
+
+int32_t cc_mlp_train_step_noalloc(float *params, float *adam_m, float *adam_v, const float *x, const float *target,
+                                  int64_t n, int64_t step, float lr, float *grad, float *loss, void *stream) {
+  g_last_error.clear();
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(CC_ERR_INVALID_ARG, "n must lie in [0, 2^31)");
+  if (!params || (n > 0 && (!x || !target))) return fail(CC_ERR_INVALID_ARG, "params, x and target must not be NULL");
+  if (!(lr >= 0.f) || !std::isfinite(lr)) return fail(CC_ERR_INVALID_ARG, "lr must be finite and >= 0");
+  if (lr > 0.f && (!adam_m || !adam_v || step < 1))
+    return fail(CC_ERR_INVALID_ARG, "an Adam step needs adam_m, adam_v and step >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const int nblk = mlp_grad_blocks((int)n);
+  float *rows = nullptr;
+  int cap = 0;
+  HIP_TRY(mlp_scratch(&rows, &cap));  // the device's static buffer: no allocation
+  if (nblk > cap)
+    return fail(CC_ERR_INVALID_ARG, "the gradient needs " + std::to_string(nblk) + " partial rows; the static buffer holds " +
+                                        std::to_string(cap));
+  HIP_TRY(launch_mlp_train_step(params, adam_m, adam_v, x, target, (int)n, (long long)step, lr, rows, nblk, grad,
                                 loss, s));
   HIP_TRY(hipStreamSynchronize(s));
   return CC_OK;

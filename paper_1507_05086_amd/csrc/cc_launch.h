@@ -88,6 +88,9 @@ hipError_t launch_async(const AsyncArgs &a, int algo, const int32_t *order_in, c
 
 // Learned-policy network: inference over a batch, one training step.
 int mlp_grad_blocks(int n);
+// The current device's static partial-row buffer (no allocation): its
+// device address and how many rows it holds.
+hipError_t mlp_scratch(float **ptr, int *rows);
 hipError_t launch_mlp_forward(const float *p, const float *x, int n, float *y, hipStream_t s);
 hipError_t launch_mlp_train_step(float *p, float *m, float *v, const float *x, const float *t, int n, long long step,
                                  float lr, float *partial, int nblk, float *grad, float *loss, hipStream_t s);

@@ -11,6 +11,8 @@
 //                LDS and writes one partial row (deterministic order);
 //   k_mlp_adam   one workgroup sums the partial rows in order and applies
 //                an Adam step with bias correction.
+#include <mutex>
+
 #include "cc_device.h"
 #include "cc_launch.h"
 
@@ -20,6 +22,8 @@ constexpr int MLP_IN = 6, MLP_H = 64;
 constexpr int MLP_P = MLP_H * MLP_IN + MLP_H + MLP_H + 1;  // 513
 constexpr int MLP_ROW = MLP_P + 1;                         // partial row: grads + sum of squared residuals
 constexpr int MLP_BS = 256;
+constexpr int MLP_MAX_BLOCKS = 1024;  // workgroups of k_mlp_grad, and partial rows
+constexpr int kMaxDevices = 64;
 
 struct Unit {
   float w[MLP_IN], b1, w2;
@@ -129,11 +133,41 @@ __global__ void __launch_bounds__(1024) k_mlp_adam(float *p, float *m, float *v,
   }
 }
 
+// Partial gradient rows for callers that cannot allocate: one row per
+// workgroup of k_mlp_grad, at most MLP_MAX_BLOCKS of them (about 2 MB).  Each
+// device that runs the library holds its own copy until the process ends.
+// Host code must never pass `scratch` itself to a kernel (on the host it is
+// a stand-in, not a device address): mlp_scratch() looks up each device's
+// address once, with hipGetSymbolAddress, and that address is what kernels
+// get.  Every call on a device shares its copy, so calls that overlap on one
+// device race.  k_mlp_grad writes every element of the rows it owns before
+// k_mlp_adam reads them, so nothing needs clearing between calls.
+static __device__ __align__(256) float scratch[MLP_MAX_BLOCKS * MLP_ROW];
+
+hipError_t mlp_scratch(float **ptr, int *rows) {
+  static std::mutex mu;
+  static float *addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the current device's copy
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<float *>(p);
+  }
+  *ptr = addr[dev];
+  *rows = MLP_MAX_BLOCKS;
+  return hipSuccess;
+}
+
 int mlp_grad_blocks(int n) {
   const int per_block = 16 * (MLP_BS / 64);  // about 16 samples per wave
   int b = (n + per_block - 1) / per_block;
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > MLP_MAX_BLOCKS) b = MLP_MAX_BLOCKS;
   return b;
 }
 
