@@ -105,7 +105,7 @@ struct Workspace {
   SchedKey sched_key;      // the practical schedule the sched buffer holds, if any
   int64_t sched_len = 0;   // its length
   float *mlp = nullptr;
-  int *host_flags = nullptr;  // pinned: done, error, has_round, fallback, phase
+  int *host_flags = nullptr;  // pinned: the device error word, read after the labels are finalized
   unsigned long long *progress = nullptr;  // pinned, coherent: k_close's progress word
   unsigned long long *progress_dev = nullptr;  // the same word as the device addresses it
   int32_t *cost_size = nullptr;
@@ -497,10 +497,11 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
         const hipError_t q = hipStreamQuery(s);
         if (q != hipErrorNotReady) {  // drained: read the state itself
           HIP_TRY(q);
-          HIP_TRY(hipMemcpyAsync(ws.host_flags, &ws.ctrl->done, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+          Ctrl now;
+          HIP_TRY(hipMemcpyAsync(&now, ws.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
           HIP_TRY(hipStreamSynchronize(s));
-          done = ws.host_flags[0] || ws.host_flags[1];
-          if (ws.host_flags[4] == PHASE_EXACT) ls.exact_seen = 1;
+          done = now.done || now.error;
+          if (now.phase == PHASE_EXACT) ls.exact_seen = 1;
           break;
         }
       }

@@ -16,6 +16,7 @@
 //   adjacency passes can hand out equal numbers of entries to every workgroup.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace ccd {
@@ -58,36 +59,54 @@ struct RoundRec {  // mirrors cc_round_record
   int64_t t_ns;  // raw wall-clock ticks here; the host converts
 };
 
+// The fields a round kernel reads before it starts its work, at the front of
+// Ctrl and in the layout of CtrlHead, so one wide load brings them all (a
+// chain of dependent scalar loads of these fields was most of the 4-5 us an
+// idle kernel cost).
+struct CtrlHead {
+  int done;                  // the run is finished (or failed)
+  int phase;                 // PHASE_LAZY (upper bounds) or PHASE_EXACT (exact degrees)
+  unsigned int n_blocked;    // C4: blocked active vertices of this round
+  unsigned int n_cedges;     // C4: conflict edges listed this round
+  long long delta;           // Delta_i of the current round
+  long long b;               // active-set size of the current round
+  long long cursor;          // first pi position not yet passed
+  long long n_rem;           // unclustered vertices
+  int d_max[DITER];          // lazy Delta search: largest exact degree found by each band pass
+  unsigned int tile_counter; // active-set scan tiles taken this round
+  unsigned long long a_pack, c_pack, n_pack, p_pack;  // active / center / newly / peel lists
+  unsigned long long r_pack[DITER];  // per band pass, the rescan list
+  unsigned long long x_pack;  // rows of degree >= DSW recounted when switching to exact degrees
+};
+
 struct Ctrl {
-  // carried across rounds
-  long long n_rem;         // unclustered vertices
-  long long delta;         // Delta_i of the current round
-  long long cursor;        // first pi position not yet passed
-  long long b;             // active-set size of the current round
+  // ---- the head (same layout as CtrlHead) ----
+  int done;
+  int phase;
+  unsigned int n_blocked, n_cedges;
+  long long delta;
+  long long b;
+  long long cursor;
+  long long n_rem;
+  int d_max[DITER];
+  unsigned int tile_counter;
+  unsigned long long a_pack, c_pack, n_pack, p_pack;
+  unsigned long long r_pack[DITER];
+  unsigned long long x_pack;
+  // ---- carried across rounds ----
   long long round;         // rounds finished
   long long n_start;       // n_i of the current round
   long long r_last;        // rank of the last active vertex
-  int done, error;
+  int error;
   int has_round;           // a round has been run since the start
   int fallback;            // learned policy fell back to the fixed rule
-  int phase;               // PHASE_LAZY (upper bounds) or PHASE_EXACT (exact degrees)
-  int pad0;
+  int select_done;         // per round: the active set is complete
   double eps_used;         // eps behind b
   float feat_conf, feat_claim, feat_eps;  // previous-round features for the learned policy
   int pad1;
   long long t_start;       // wall clock at round start
-  // per round
-  unsigned long long a_pack, c_pack, n_pack, p_pack;  // active / center / newly / peel lists
-  unsigned int tile_counter;
-  int select_done;
-  unsigned int n_blocked, n_cedges;
-  unsigned long long conflicts;
-  // lazy Delta search: per band pass, the rescan list and the largest exact degree found
-  unsigned long long r_pack[DITER];
-  int d_max[DITER];
-  int pad2;
-  unsigned long long x_pack;  // rows of degree >= DSW recounted when switching to exact degrees
-  unsigned long long x_low[64];  // adjacency entries of the lower-degree rows recounted then (spread)
+  unsigned long long conflicts;  // per round: ClusterWild! conflict marks counted by k_clear
+  unsigned long long x_low[64];  // adjacency entries of the lower-degree rows recounted at the switch (spread)
   // bound buckets: entries per level (capacity fixed per graph)
   unsigned int lvl_cnt[NLVL];
   // run totals
@@ -99,6 +118,39 @@ struct Ctrl {
   // unclustered neighbour: a center that claims nobody), spread the same way
   unsigned long long spread_lone[64];
 };
+static_assert(sizeof(CtrlHead) == 128, "the head is one 128-byte line");
+static_assert(offsetof(Ctrl, done) == offsetof(CtrlHead, done) && offsetof(Ctrl, phase) == offsetof(CtrlHead, phase) &&
+                  offsetof(Ctrl, n_blocked) == offsetof(CtrlHead, n_blocked) &&
+                  offsetof(Ctrl, n_cedges) == offsetof(CtrlHead, n_cedges) &&
+                  offsetof(Ctrl, delta) == offsetof(CtrlHead, delta) && offsetof(Ctrl, b) == offsetof(CtrlHead, b) &&
+                  offsetof(Ctrl, cursor) == offsetof(CtrlHead, cursor) &&
+                  offsetof(Ctrl, n_rem) == offsetof(CtrlHead, n_rem) &&
+                  offsetof(Ctrl, d_max) == offsetof(CtrlHead, d_max) &&
+                  offsetof(Ctrl, tile_counter) == offsetof(CtrlHead, tile_counter) &&
+                  offsetof(Ctrl, a_pack) == offsetof(CtrlHead, a_pack) &&
+                  offsetof(Ctrl, c_pack) == offsetof(CtrlHead, c_pack) &&
+                  offsetof(Ctrl, n_pack) == offsetof(CtrlHead, n_pack) &&
+                  offsetof(Ctrl, p_pack) == offsetof(CtrlHead, p_pack) &&
+                  offsetof(Ctrl, r_pack) == offsetof(CtrlHead, r_pack) &&
+                  offsetof(Ctrl, x_pack) == offsetof(CtrlHead, x_pack),
+              "Ctrl starts with CtrlHead's layout");
+
+// The head as the kernel starts: eight independent 16-byte scalar loads
+// issued together (the values were written by earlier kernels of the
+// stream).  The empty asm takes every loaded value, so the compiler can
+// neither split the head into loads made one after another behind each
+// test nor sink them past the early exits.
+__device__ inline CtrlHead ctrl_head(const Ctrl *c) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(c);
+  uint4 q[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) q[i] = p[i];
+#pragma unroll
+  for (int i = 0; i < 8; i++) asm volatile("" ::"s"(q[i].x), "s"(q[i].y), "s"(q[i].z), "s"(q[i].w));
+  CtrlHead h;
+  __builtin_memcpy(&h, q, sizeof(h));
+  return h;
+}
 
 // A listed vertex's row: start of its adjacency in col, its degree and its
 // rank in pi.  Carried along the active and center lists so the passes over

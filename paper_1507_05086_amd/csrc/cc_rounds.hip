@@ -182,8 +182,10 @@ __device__ inline long long band_floor(int pass, long long T) {
   return (long long)ceilf(band_factor(pass) * (float)T);
 }
 
-// State of the search after `done` passes (every thread computes the same).
-__device__ inline DSearch dsearch(const Ctrl *c, int done) {
+// State of the search after `done` passes (every thread computes the same);
+// C is Ctrl or a CtrlHead snapshot of it.
+template <class C>
+__device__ inline DSearch dsearch(const C *c, int done) {
   DSearch s{0, 0, -1, 0, 0};
   if (c->phase != PHASE_LAZY) return s;
   long long T = c->delta;
@@ -215,8 +217,9 @@ __device__ inline DSearch dsearch(const Ctrl *c, int done) {
 template <int IT>
 __global__ void __launch_bounds__(BS) k_dscan(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
-  const DSearch s = dsearch(c, IT);
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
+  const DSearch s = dsearch(&h, IT);
   if (!s.pending) return;
   const int kL = level_of(s.L < DSW ? DSW : s.L), kT = NLVL - 1;
   int64_t base[NLVL + 1];
@@ -254,8 +257,9 @@ __global__ void __launch_bounds__(BS) k_dscan(Ws w) {
 template <int IT>
 __global__ void __launch_bounds__(BS) k_rescan(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
-  const DSearch s = dsearch(c, IT);
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
+  const DSearch s = dsearch(&h, IT);
   if (!s.pending) return;
   __shared__ int lcnt[TW];
   __shared__ int s_max, s_nmv;
@@ -269,7 +273,7 @@ __global__ void __launch_bounds__(BS) k_rescan(Ws w) {
     s_nmv = 0;
   }
   __syncthreads();
-  const unsigned long long rp = c->r_pack[IT];
+  const unsigned long long rp = h.r_pack[IT];
   const int64_t cnt = pk_cnt(rp) < w.rcap ? pk_cnt(rp) : w.rcap;
   unsigned long long *ra = w.racc + IT * w.rcap;
   auto finalize = [&](int32_t v, int r) {
@@ -327,8 +331,9 @@ __global__ void __launch_bounds__(BS) k_rescan(Ws w) {
 // round) ...
 __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
-  const DSearch s = dsearch(c, DITER);
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
+  const DSearch s = dsearch(&h, DITER);
   if (!s.switching) return;
   unsigned long long *xacc = (unsigned long long *)w.awork;
   __shared__ StageBuf<2 * BS> sb;
@@ -354,8 +359,9 @@ __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
 // about one length and no search or barrier is needed.
 __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
-  const DSearch s = dsearch(c, DITER);
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
+  const DSearch s = dsearch(&h, DITER);
   if (!s.switching) return;
   __shared__ int lcnt[TW];
   __shared__ int s_hist[HLDS];
@@ -363,7 +369,7 @@ __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
   for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
   __syncthreads();
   unsigned long long *xacc = (unsigned long long *)w.awork;
-  const unsigned long long xp = c->x_pack;
+  const unsigned long long xp = h.x_pack;
   auto finalize = [&](int32_t v, int r) {
     w.ub[v] = r;
     if (r > 0 && r < HLDS) atomicAdd(&s_hist[r], 1);
@@ -543,19 +549,20 @@ __device__ inline unsigned load_slots(const Ws &w, int64_t base, int64_t end, in
 // The next B_i unclustered vertices of pi (Algorithm 2's active set).
 __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
   __shared__ unsigned s_tile;
   __shared__ int s_stop;
   __shared__ long long s_excl;
   __shared__ int64_t sh[SEL_BS / 64 + 1];
   __shared__ unsigned long long s_base;
-  const long long B = c->b, cur0 = c->cursor;
-  const bool exact = c->phase == PHASE_EXACT;
+  const long long B = h.b, cur0 = h.cursor;
+  const bool exact = h.phase == PHASE_EXACT;
   const int64_t n = w.n;
   // Workgroups this round can use: B_i unclustered are spread over the
   // positions ahead with density n_i / (n - cursor); extra groups would only
   // grab tiles past the end of the active set.
-  const long long ahead = n - cur0, n_i = c->n_rem > 0 ? c->n_rem : 1;
+  const long long ahead = n - cur0, n_i = h.n_rem > 0 ? h.n_rem : 1;
   const long long need_pos = (long long)((double)B * (double)ahead / (double)n_i) + TSEL;
   if ((long long)blockIdx.x > need_pos / TSEL) return;
   for (;;) {
@@ -615,11 +622,12 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
 // No prefix count is needed, so tiles are dealt statically.
 __global__ void __launch_bounds__(SEL_BS) k_select_range(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
   __shared__ int64_t sh[SEL_BS / 64 + 1];
   __shared__ unsigned long long s_base;
-  const int64_t cur0 = c->cursor;
-  const int64_t end = cur0 + c->b < w.n ? cur0 + c->b : w.n;
+  const int64_t cur0 = h.cursor;
+  const int64_t end = cur0 + h.b < w.n ? cur0 + h.b : w.n;
   for (int64_t t = blockIdx.x; cur0 + t * TSEL < end; t += gridDim.x) {
     const int64_t base = cur0 + t * TSEL + (int64_t)threadIdx.x * SIPT;
     int32_t vv[SIPT];
@@ -633,8 +641,9 @@ __global__ void __launch_bounds__(SEL_BS) k_select_range(Ws w) {
 
 __global__ void __launch_bounds__(BS) k_elect(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
-  const unsigned long long ap = c->a_pack;
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
+  const unsigned long long ap = h.a_pack;
   lb_walk(w.alist, w.awork, pk_cnt(ap), pk_work(ap), w.off, w.col, nullptr, w.ainfo, [&](Items &it) {
     uint8_t su[IPT];
 #pragma unroll
@@ -663,10 +672,11 @@ __global__ void __launch_bounds__(BS) k_elect(Ws w) {
 // Roots (no earlier active neighbour) are centers at once; the rest wait.
 __global__ void __launch_bounds__(BS) k_classify(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
   __shared__ StageBufI<2 * BS> sb;
   stage_init(sb);
-  const int64_t na = pk_cnt(c->a_pack);
+  const int64_t na = pk_cnt(h.a_pack);
   const int64_t per = ((na + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
   const int64_t a0 = (int64_t)blockIdx.x * per, a1 = a0 + per < na ? a0 + per : na;
   for (int64_t ib = a0; ib < a1; ib += BS) {
@@ -865,10 +875,11 @@ __device__ void resolve_rows(Ws &w, Ctrl *c, int64_t nb) {
 
 __global__ void __launch_bounds__(RBS) k_resolve(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
-  const int64_t nb = c->n_blocked;
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
+  const int64_t nb = h.n_blocked;
   if (nb == 0) return;
-  const int64_t ne = c->n_cedges;
+  const int64_t ne = h.n_cedges;
   if (ne <= w.cedge_cap) resolve_listed(w, c, nb, ne);
   else resolve_rows(w, c, nb);
   __syncthreads();
@@ -881,9 +892,10 @@ constexpr int CLAIM_CAP = 2 * TW;  // staged newly claimed vertices (a tile adds
 
 __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
   const bool c4 = w.algo == ALGO_C4;
-  const unsigned long long lp = c4 ? c->c_pack : c->a_pack;
+  const unsigned long long lp = c4 ? h.c_pack : h.a_pack;
   const int32_t *list = c4 ? w.clist : w.alist;
   const int64_t *work = c4 ? w.cwork : w.awork;
   const RowInfo *info = c4 ? w.cinfo : w.ainfo;
@@ -945,15 +957,16 @@ __device__ inline void hist_add(int *s_hist, int *g_hist, int d, int x) {
 // peel; it only leaves the degree histogram.
 __global__ void __launch_bounds__(BS) k_clear(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done) return;
+  const CtrlHead h = ctrl_head(c);
+  if (h.done) return;
   __shared__ StageBuf<2 * BS> sp;
   __shared__ int s_hist[HLDS];
   for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
   stage_init(sp);
-  const bool cw = w.algo == ALGO_CW, exact = c->phase == PHASE_EXACT;
-  const int64_t nc = pk_cnt(cw ? c->a_pack : c->c_pack);
+  const bool cw = w.algo == ALGO_CW, exact = h.phase == PHASE_EXACT;
+  const int64_t nc = pk_cnt(cw ? h.a_pack : h.c_pack);
   const int32_t *centers = cw ? w.alist : w.clist;
-  const int64_t nn = nc + pk_cnt(c->n_pack);
+  const int64_t nn = nc + pk_cnt(h.n_pack);
   unsigned conf = 0;
   const int64_t per = ((nn + gridDim.x - 1) / gridDim.x + BS - 1) / BS * BS;
   const int64_t i0 = (int64_t)blockIdx.x * per, i1 = i0 + per < nn ? i0 + per : nn;
@@ -977,7 +990,7 @@ __global__ void __launch_bounds__(BS) k_clear(Ws w) {
     if (sp.cnt > BS) stage_flush(sp, &c->p_pack, w.plist, w.pwork);
   }
   stage_flush(sp, &c->p_pack, w.plist, w.pwork);
-  const int64_t tiles = (int64_t)c->tile_counter + 1;
+  const int64_t tiles = (int64_t)h.tile_counter + 1;
   for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < tiles && t < w.tstat_cap;
        t += (int64_t)gridDim.x * BS)
     w.tstat[t] = 0;
@@ -998,13 +1011,14 @@ __global__ void __launch_bounds__(BS) k_clear(Ws w) {
 
 __global__ void __launch_bounds__(BS) k_peel(Ws w) {
   Ctrl *c = w.ctrl;
-  if (c->done || c->phase != PHASE_EXACT) return;
+  const CtrlHead h = ctrl_head(c);
+  if (h.done || h.phase != PHASE_EXACT) return;
   __shared__ int s_hist[HLDS];
   __shared__ unsigned s_atom;
   for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
   if (threadIdx.x == 0) s_atom = 0;
   __syncthreads();
-  const unsigned long long pp = c->p_pack;
+  const unsigned long long pp = h.p_pack;
   lb_walk(w.plist, w.pwork, pk_cnt(pp), pk_work(pp), w.off, w.col, nullptr, nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++)
