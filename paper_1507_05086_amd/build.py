@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcc.so")
-SOURCES = ["cc_api.cpp", "cc_schedule.cpp", "cc_rounds.hip", "cc_async.hip", "cc_graph.hip", "cc_batched.hip",
-           "cc_mlp.hip"]
+SOURCES = ["cc_api.cpp", "cc_schedule.cpp", "cc_rounds.hip", "cc_order.hip", "cc_async.hip", "cc_graph.hip",
+           "cc_batched.hip", "cc_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",

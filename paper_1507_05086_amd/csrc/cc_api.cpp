@@ -100,6 +100,8 @@ struct Workspace {
   RoundRec *trace = nullptr;
   int64_t trace_cap = 0;
   int32_t *order_buf = nullptr, *label_buf = nullptr, *iorder = nullptr;
+  uint8_t *omap_buf = nullptr;  // bucketed order mapping scratch (large n only)
+  OrderMap omap{};
   int64_t *sched = nullptr;
   int64_t sched_cap = 0;
   SchedKey sched_key;      // the practical schedule the sched buffer holds, if any
@@ -167,7 +169,7 @@ void free_ws(Workspace &w) {
   void *ptrs[] = {w.rank, w.lab, w.ub, w.unc, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
                   w.awork, w.cwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist, w.plist, w.pwork,
                   w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf, w.label_buf, w.sched, w.mlp, w.ainfo, w.cinfo,
-                  w.iorder, w.cost_size, w.cost_acc, w.dev_err, w.bpos, w.bpend, w.bdec, w.bdep, w.bq, w.bradj};
+                  w.iorder, w.cost_size, w.cost_acc, w.dev_err, w.bpos, w.bpend, w.bdec, w.bdep, w.bq, w.bradj, w.omap_buf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (w.host_flags) (void)hipHostFree(w.host_flags);
@@ -251,6 +253,10 @@ int32_t ensure_ws(cc_graph *g) {
   HIP_TRY(dalloc(&w.order_buf, n));
   HIP_TRY(dalloc(&w.label_buf, n));
   HIP_TRY(dalloc(&w.iorder, n));
+  if (order_map_applies(n)) {
+    HIP_TRY(dalloc(&w.omap_buf, order_map_bytes(n)));
+    w.omap = order_map_layout(n, w.omap_buf);
+  }
   HIP_TRY(dalloc(&w.mlp, CC_MLP_PARAMS));
   HIP_TRY(dalloc(&w.cost_size, n));
   HIP_TRY(dalloc(&w.cost_acc, 2 * (size_t)g->num_graphs));
@@ -391,6 +397,7 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   w.order_in = d_order;
   w.perm = g->perm;
   w.iperm = g->iperm;
+  w.order_mapped = ws.omap_buf != nullptr;
   w.max_deg = g->max_deg;
   w.low_start = g->low_start;
   w.iso_start = g->iso_start;
@@ -452,7 +459,11 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   // the call then returns at once.
   __atomic_store_n(ws.progress, 0ull, __ATOMIC_RELEASE);  // nothing of this handle is in flight
   HIP_TRY(hipMemsetAsync(ws.ctrl, 0, sizeof(Ctrl), s));
-  HIP_TRY(hipMemsetAsync(ws.state, 0, (size_t)n, s));  // k_check_order marks the vertices pi names
+  if (w.order_mapped) {
+    HIP_TRY(launch_order_map(ws.omap, d_order, g->perm, n, ws.iorder, ws.ctrl, s));
+  } else {
+    HIP_TRY(hipMemsetAsync(ws.state, 0, (size_t)n, s));  // k_check_order marks the vertices pi names
+  }
   HIP_TRY(hipMemsetAsync(ws.hist, 0, sizeof(int) * (size_t)ws.hist_len, s));
   if (g->lvl_total > 0)
     HIP_TRY(hipMemcpyAsync(ws.lvl, g->lvl_init, sizeof(int32_t) * (size_t)g->lvl_total, hipMemcpyDeviceToDevice, s));

@@ -175,6 +175,7 @@ struct Ws {
   const int32_t *order_in;  // the caller's pi (input ids)
   const int32_t *perm;      // input id -> internal id
   const int32_t *iperm;     // internal id -> input id
+  int order_mapped;         // pi was mapped and checked by the bucketed passes: no marks in state
   // per-vertex arrays
   int32_t *rank, *lab, *ub;
   uint32_t *unc;

@@ -65,6 +65,32 @@ hipError_t launch_relabel(const int64_t *off, const int32_t *col, const int64_t 
                           int64_t *blocksum, int32_t *rcol, int64_t *first_low, int64_t *first_isolated,
                           hipStream_t s);
 
+// pi mapped into internal ids and checked as a permutation, in bucketed
+// passes (cc_order.hip) for OM_MIN_N < n <= OM_MAX_BUCKETS * OM_SIZE; other
+// sizes gather directly.  Bucket kb of positions and bucket vb of ids hold
+// OM_SIZE each.  The scratch (order_map_bytes(n), one device allocation) is
+// laid out by order_map_layout.  A failed check sets ERR_PERM in ctrl.
+constexpr int OM_SHIFT = 15;
+constexpr int64_t OM_SIZE = int64_t(1) << OM_SHIFT;
+constexpr int OM_MAX_BUCKETS = 2048;
+constexpr int64_t OM_MIN_N = int64_t(1) << 22;
+struct OrderMap {
+  int nk, nv;               // position buckets, id buckets
+  int nkt, nvt;             // 64-bucket tiles of each
+  unsigned *cnt;            // [nk][nv] entries of kb in vb; then where (kb, vb) starts in ent, by row
+  unsigned *pt;             // [nv][nk] where (kb, vb) starts in ent, by column
+  unsigned *qt;             // [nv][nk] where (kb, vb) starts in pent, by column
+  unsigned *csum, *rsum;    // [nkt][nv] column and [nvt][nk] row sums of 64 x 64 tiles
+  unsigned *vstart;         // [nv + 1] start of each id bucket in ent
+  unsigned *ent;            // [n] k low bits | (id low bits << OM_SHIFT), by id bucket, then kb
+  unsigned long long *pent; // [n] (internal id << OM_SHIFT) | k low bits, by position bucket
+};
+bool order_map_applies(int64_t n);
+size_t order_map_bytes(int64_t n);
+OrderMap order_map_layout(int64_t n, void *base);
+hipError_t launch_order_map(const OrderMap &m, const int32_t *order_in, const int32_t *perm, int64_t n,
+                            int32_t *iorder, Ctrl *ctrl, hipStream_t s);
+
 // Asynchronous C4 / ClusterWild! (Algorithm 3): one persistent launch, no
 // rounds.  rank and lab are workspace arrays of n; order is pi in internal
 // ids (written by the launch from order_in through perm into iorder).

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(BS) k_check_order(Ws w) {
 __global__ void __launch_bounds__(BS) k_init(Ws w, const unsigned *lvl_init_cnt) {
   const int64_t n = w.n;
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
-    if (w.state[v] != ORDER_SEEN) set_error(w.ctrl, ERR_PERM);  // no entry of pi names v
+    if (!w.order_mapped && w.state[v] != ORDER_SEEN) set_error(w.ctrl, ERR_PERM);  // no entry of pi names v
     w.lab[v] = INF;
     w.state[v] = UNCL;
     w.flag[v] = 0;
@@ -1247,7 +1247,7 @@ static inline unsigned grid_for(int64_t items, unsigned cap) {
 }
 
 hipError_t launch_init(const Ws &w, const unsigned *lvl_init_cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_order, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w);
+  if (!w.order_mapped) hipLaunchKernelGGL(k_check_order, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w);
   hipLaunchKernelGGL(k_init, dim3(grid_for(w.n, 4096)), dim3(BS), 0, s, w, lvl_init_cnt);
   hipLaunchKernelGGL(k_close, dim3(1), dim3(64), 0, s, w);
   return hipGetLastError();
