@@ -623,7 +623,7 @@ int32_t run_async(cc_graph *g, int algo, const int32_t *order, int32_t *labels, 
   AsyncArgs a{g->roff, g->rcol, n, g->iso_start, ws.iorder, ws.rank, ws.lab, ws.ctrl, ws.xlist, ws.plist, n};
   // labels reach the caller only on success
   HIP_TRY(launch_async(a, algo, d_order, g->perm, ws.iorder, ws.label_buf, stats ? (int)stats->async_waves : 0, s,
-                       ev0, ev1));
+                       ev0, ev1, ws.omap_buf ? &ws.omap : nullptr));
   Ctrl hc;
   HIP_TRY(hipMemcpyAsync(&hc, ws.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));

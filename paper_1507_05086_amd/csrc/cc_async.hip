@@ -263,9 +263,11 @@ __global__ void __launch_bounds__(BS) k_async_order(AsyncArgs a, const int32_t *
   }
 }
 
-__global__ void __launch_bounds__(BS) k_async_init(AsyncArgs a) {
+// check: the permutation check still to finish (after k_async_order; the
+// bucketed mapping checks by itself)
+__global__ void __launch_bounds__(BS) k_async_init(AsyncArgs a, int check) {
   for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < a.n; v += (int64_t)gridDim.x * BS) {
-    if (a.rank[v] < 0) set_error(a.ctrl, ERR_PERM);  // no entry of pi names v
+    if (check && a.rank[v] < 0) set_error(a.ctrl, ERR_PERM);  // no entry of pi names v
     a.lab[v] = INF;
   }
 }
@@ -300,11 +302,16 @@ static unsigned grid_n(int64_t n) {
 }
 
 hipError_t launch_async(const AsyncArgs &a, int algo, const int32_t *order_in, const int32_t *perm, int32_t *iorder,
-                        int32_t *labels, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  hipError_t e = hipMemsetAsync(a.rank, 0xFF, sizeof(int32_t) * (size_t)a.n, s);  // every rank -1
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_async_order, dim3(grid_n(a.n)), dim3(BS), 0, s, a, order_in, perm, iorder);
-  hipLaunchKernelGGL(k_async_init, dim3(grid_n(a.n)), dim3(BS), 0, s, a);
+                        int32_t *labels, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                        const OrderMap *om) {
+  hipError_t e;
+  if (om) {
+    if ((e = launch_order_map(*om, order_in, perm, a.n, iorder, a.ctrl, s, a.rank)) != hipSuccess) return e;
+  } else {
+    if ((e = hipMemsetAsync(a.rank, 0xFF, sizeof(int32_t) * (size_t)a.n, s)) != hipSuccess) return e;  // every rank -1
+    hipLaunchKernelGGL(k_async_order, dim3(grid_n(a.n)), dim3(BS), 0, s, a, order_in, perm, iorder);
+  }
+  hipLaunchKernelGGL(k_async_init, dim3(grid_n(a.n)), dim3(BS), 0, s, a, om ? 0 : 1);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   auto kern = algo == ALGO_C4 ? k_async<ALGO_C4> : k_async<ALGO_CW>;

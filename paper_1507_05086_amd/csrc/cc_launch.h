@@ -88,8 +88,9 @@ struct OrderMap {
 bool order_map_applies(int64_t n);
 size_t order_map_bytes(int64_t n);
 OrderMap order_map_layout(int64_t n, void *base);
+// rank (optional): also rank[iorder[k]] = k, the inverse of pi in internal ids.
 hipError_t launch_order_map(const OrderMap &m, const int32_t *order_in, const int32_t *perm, int64_t n,
-                            int32_t *iorder, Ctrl *ctrl, hipStream_t s);
+                            int32_t *iorder, Ctrl *ctrl, hipStream_t s, int32_t *rank = nullptr);
 
 // Asynchronous C4 / ClusterWild! (Algorithm 3): one persistent launch, no
 // rounds.  rank and lab are workspace arrays of n; order is pi in internal
@@ -109,8 +110,10 @@ struct AsyncArgs {
 // waves > 0 limits the launch to that many waves (1: pi strictly in order,
 // 64 positions at a time); 0 fills the device.  ev0 / ev1 (optional) bracket
 // the asynchronous kernel itself.
+// om: the bucketed mapping of pi when it applies to this n, else nullptr.
 hipError_t launch_async(const AsyncArgs &a, int algo, const int32_t *order_in, const int32_t *perm, int32_t *iorder,
-                        int32_t *labels, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+                        int32_t *labels, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                        const OrderMap *om);
 
 // Learned-policy network: inference over a batch, one training step.
 int mlp_grad_blocks(int n);

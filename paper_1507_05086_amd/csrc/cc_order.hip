@@ -311,7 +311,8 @@ constexpr size_t OM_PLACE_LDS = sizeof(int32_t) * OM_SIZE;
 // Per id bucket: every entry mapped through the bucket's slice of perm and
 // its id marked; the bucket holds a repeated id exactly when fewer bits are
 // set than it has entries.
-__global__ void __launch_bounds__(OM_BS) k_om_gather(OrderMap m, const int32_t *perm, int64_t n, Ctrl *ctrl) {
+__global__ void __launch_bounds__(OM_BS) k_om_gather(OrderMap m, const int32_t *perm, int64_t n, Ctrl *ctrl,
+                                                    int32_t *rank) {
   extern __shared__ __align__(16) uint8_t lds[];
   int32_t *slice = reinterpret_cast<int32_t *>(lds);
   unsigned *bits = reinterpret_cast<unsigned *>(slice + OM_SIZE);
@@ -369,7 +370,10 @@ __global__ void __launch_bounds__(OM_BS) k_om_gather(OrderMap m, const int32_t *
         if (e < e1) {
           const unsigned kl = x[jb + j] & OM_MASK, vl = x[jb + j] >> OM_SHIFT;
           atomicOr(&bits[vl >> 5], 1u << (vl & 31));
-          m.pent[qcol[kb[j]] + (e - pcol[kb[j]])] = ((unsigned long long)(uint32_t)slice[vl] << OM_SHIFT) | kl;
+          const int32_t vi = slice[vl];
+          m.pent[qcol[kb[j]] + (e - pcol[kb[j]])] = ((unsigned long long)(uint32_t)vi << OM_SHIFT) | kl;
+          // the renumbering keeps runs of input ids together, so these land in few runs
+          if (rank) rank[vi] = (int32_t)((unsigned)kb[j] * OM_SIZE + kl);
         }
       }
     }
@@ -432,7 +436,7 @@ OrderMap order_map_layout(int64_t n, void *base) {
 }
 
 hipError_t launch_order_map(const OrderMap &m, const int32_t *order_in, const int32_t *perm, int64_t n,
-                            int32_t *iorder, Ctrl *ctrl, hipStream_t s) {
+                            int32_t *iorder, Ctrl *ctrl, hipStream_t s, int32_t *rank) {
   static hipError_t attr = [] {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_om_scatter),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)OM_SCATTER_LDS);
@@ -451,7 +455,7 @@ hipError_t launch_order_map(const OrderMap &m, const int32_t *order_in, const in
   hipLaunchKernelGGL(k_om_scan, dim3(1), dim3(OM_BS), 0, s, m);
   hipLaunchKernelGGL(k_om_offsets, dim3(tiles), dim3(OM_TBS), 0, s, m);
   hipLaunchKernelGGL(k_om_scatter, dim3(m.nk), dim3(OM_BS), OM_SCATTER_LDS, s, m, order_in, n);
-  hipLaunchKernelGGL(k_om_gather, dim3(m.nv), dim3(OM_BS), OM_GATHER_LDS, s, m, perm, n, ctrl);
+  hipLaunchKernelGGL(k_om_gather, dim3(m.nv), dim3(OM_BS), OM_GATHER_LDS, s, m, perm, n, ctrl, rank);
   hipLaunchKernelGGL(k_om_place, dim3(m.nk), dim3(OM_BS), OM_PLACE_LDS, s, m, n, iorder);
   return hipGetLastError();
 }

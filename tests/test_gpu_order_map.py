@@ -7,7 +7,9 @@ buckets, against the oracle, and feed the check every kind of input that is
 not a permutation: a repeated id whose bucket counts still balance (only the
 per-bucket bitmap can see it), a repeat across buckets, ids out of range on
 either side, the last id repeated, and pi all zero.  A failed check must
-leave a device label buffer untouched and the handle usable.
+leave a device label buffer untouched and the handle usable.  The
+asynchronous variants take the same mapping, which also writes each
+vertex's rank.
 """
 import numpy as np
 import pytest
@@ -75,15 +77,33 @@ def _bad_orders(n, seed):
     return good, cases
 
 
+def test_bucketed_async(cc, er4m):
+    g, gh = er4m
+    order = graphgen.permutation(g.n, 44)
+    torch = torch_cuda()
+    lab, _ = cc.cc_c4_async(gh, torch.from_numpy(order).cuda())
+    torch.cuda.synchronize()
+    assert_labels_equal(lab.cpu().numpy(), oracle.kwikcluster(g.off, g.col, order), "async C4")
+    # one wave: positions in order, 64 at a time, so ClusterWild! is the BSP
+    # oracle with batches of 64 positions
+    lab, _ = cc.cc_clusterwild_async(gh, torch.from_numpy(order).cuda(), waves=1)
+    torch.cuda.synchronize()
+    sched = np.full((g.n + 63) // 64, 64, dtype=np.int64)
+    ref = oracle.bsp_positions(oracle.CW, g.off, g.col, order, sched)
+    assert_labels_equal(lab.cpu().numpy(), ref.labels, "async ClusterWild!, one wave")
+
+
 def test_bucketed_rejects_non_permutations(cc, er4m):
     torch = torch_cuda()
     g, gh = er4m
     good, cases = _bad_orders(g.n, 43)
     out = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+    calls = (lambda o: cc.cc_c4(gh, o, 0.5, labels=out), lambda o: cc.cc_clusterwild(gh, o, 0.5, labels=out),
+             lambda o: cc.cc_c4_async(gh, o, labels=out), lambda o: cc.cc_clusterwild_async(gh, o, labels=out))
     for name, bad in cases.items():
-        for fn in (cc.cc_c4, cc.cc_clusterwild):
+        for fn in calls:
             with pytest.raises(cc.CCError) as ei:
-                fn(gh, torch.from_numpy(np.ascontiguousarray(bad, dtype=np.int32)).cuda(), 0.5, labels=out)
+                fn(torch.from_numpy(np.ascontiguousarray(bad, dtype=np.int32)).cuda())
             assert ei.value.code == cc.CC_ERR_NOT_PERMUTATION, name
             torch.cuda.synchronize()
             assert bool((out == -7).all()), name
