@@ -83,7 +83,13 @@ def measured_traffic(workload):
     return d
 
 
-CALL_FIRST, CALL_LAST = "k_check_order", "k_finalize"
+# a call's first kernel: the bucketed mapping of pi (large graphs) or the direct one
+CALL_FIRST, CALL_LAST = ("k_om_count", "k_check_order"), "k_finalize"
+
+
+def kernel_short_name(name):
+    """'ccd::(anonymous namespace)::k_om_count(ccd::OrderMap, ...)' -> 'k_om_count'."""
+    return name.replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1]
 
 
 def summarize_counters(fetch_csv, write_csv, workload, copy_mb):
@@ -116,7 +122,7 @@ def summarize_counters(fetch_csv, write_csv, workload, copy_mb):
         out[f"{key}_copy_factor"] = round(factor, 4)
         calls, cur = [], None
         for name, b in seq:
-            short = name.split("(")[0].split("::")[-1]
+            short = kernel_short_name(name)
             if short.startswith(CALL_FIRST):
                 cur = [0.0, 0]
             if cur is not None:
