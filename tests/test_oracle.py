@@ -376,3 +376,88 @@ def test_trace_fields_from_definitions(family, algo, eps):
          else graphgen.chung_lu(5000, 2.1, 16.0, seed=51))
     order = graphgen.permutation(g.n, 7)
     _replay_checks(g, order, algo, eps)
+
+
+# ----------------------- ClusterWild! as a peeling of the graph without the
+# edges among same-round active vertices (the paper's analysis of CW)
+
+def _peel(n, adj, centers):
+    """Greedy peeling: each center in turn takes itself and its unclustered
+    neighbours in `adj`.  Returns the labels and the number of bad triangles
+    (three vertices, exactly two pairs adjacent) that contain the center and
+    two vertices still unclustered at its turn."""
+    unc = set(range(n))
+    labels = [-1] * n
+    bad = 0
+    for c in centers:
+        assert c in unc, "a center was already clustered at its turn"
+        rest = sorted(unc - {c})
+        for i, a in enumerate(rest):
+            for b in rest[i + 1:]:
+                if (a in adj[c]) + (b in adj[c]) + (b in adj[a]) == 2:
+                    bad += 1
+        for u in {c} | (adj[c] & unc):
+            labels[u] = c
+            unc.discard(u)
+    assert not unc, "the centers left vertices unclustered"
+    return np.array(labels, dtype=np.int32), bad
+
+
+def _active_sets(r, order, n):
+    """The active set of every round, from the trace's r_i and the round in
+    which each vertex was clustered."""
+    out, prev = [], -1
+    for i in range(r.rounds):
+        seg = order[prev + 1:int(r.trace["r_i"][i]) + 1]
+        out.append([int(v) for v in seg if r.round_of[v] >= i])
+        prev = int(r.trace["r_i"][i])
+    return out
+
+
+@pytest.mark.parametrize("eps", [0.5, 2.0, 8.0])
+@pytest.mark.parametrize("seed", range(6))
+def test_cw_is_kwikcluster_peeling_of_the_graph_without_active_edges(seed, eps):
+    """The paper bounds ClusterWild!'s cost by treating the edges between two
+    vertices active in the same round as deleted: on that graph G', CW is a
+    greedy peeling that takes the centers round by round in pi order, and
+    any greedy peeling costs exactly the bad triangles at each center among
+    the vertices still unclustered (section Approximation ratio, the two
+    lemmas on the cost of greedy peelings and of CW).  On G the deleted
+    edges are cut as well.  So, exactly: CW's labels are that peeling's, and
+    cost_G = bad triangles of G' at the centers + deleted edges."""
+    g = graphgen.erdos_renyi(28, 4.0 + seed, seed=300 + seed)
+    order = graphgen.permutation(g.n, 400 + seed)
+    rank = np.empty(g.n, dtype=np.int64)
+    rank[order] = np.arange(g.n)
+    adj = [set(g.col[g.off[v]:g.off[v + 1]].tolist()) for v in range(g.n)]
+    r = oracle.bsp(oracle.CW, g.off, g.col, order, eps, with_round_of=True)
+    acts = _active_sets(r, order, g.n)
+    gp = [set(s) for s in adj]
+    deleted = 0
+    for a in acts:
+        sa = set(a)
+        for v in a:
+            for u in adj[v] & sa:
+                if u > v:
+                    deleted += 1
+                gp[v].discard(u)
+    centers = [v for a in acts for v in sorted(a, key=lambda x: rank[x])]
+    labels, bad = _peel(g.n, gp, centers)
+    assert np.array_equal(labels, r.labels)
+    assert oracle.cost(g.off, g.col, r.labels) == bad + deleted
+    if eps >= 2.0:
+        assert deleted > 0  # the larger batches put adjacent vertices in one active set
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_kwikcluster_cost_is_its_bad_triangles(seed):
+    """The same lemma for KwikCluster (nothing deleted): the cost equals the
+    bad triangles at the centers, taken in pi order."""
+    g = graphgen.erdos_renyi(30, 5.0, seed=500 + seed)
+    order = graphgen.permutation(g.n, 600 + seed)
+    adj = [set(g.col[g.off[v]:g.off[v + 1]].tolist()) for v in range(g.n)]
+    kc = oracle.kwikcluster(g.off, g.col, order)
+    centers = [int(v) for v in order if kc[v] == v]
+    labels, bad = _peel(g.n, adj, centers)
+    assert np.array_equal(labels, kc)
+    assert oracle.cost(g.off, g.col, kc) == bad
