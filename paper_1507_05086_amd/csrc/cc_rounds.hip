@@ -67,11 +67,17 @@ __global__ void __launch_bounds__(BS) k_check_order(Ws w) {
   }
 }
 
+// An isolated vertex (id >= iso_start) has no neighbour to read its state,
+// flag or bound, and k_select settles it by its id alone, so only a partial
+// run (whose k_finalize reads its label) and the direct check of pi (which
+// reads its mark) visit those ids.
 __global__ void __launch_bounds__(BS) k_init(Ws w, const unsigned *lvl_init_cnt) {
   const int64_t n = w.n;
-  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS) {
+  const int64_t end = (w.order_mapped && w.max_rounds == 0) ? w.iso_start : n;
+  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < end; v += (int64_t)gridDim.x * BS) {
     if (!w.order_mapped && w.state[v] != ORDER_SEEN) set_error(w.ctrl, ERR_PERM);  // no entry of pi names v
     w.lab[v] = INF;
+    if (v >= w.iso_start) continue;
     w.state[v] = UNCL;
     w.flag[v] = 0;
     w.ub[v] = (int32_t)(w.off[v + 1] - w.off[v]);
