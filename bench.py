@@ -208,10 +208,11 @@ def timed_call(cc, torch, fn, gh, order, eps, lab):
     return st, e0.elapsed_time(e1)
 
 
-def bench_learned(cc, torch, gh, order, lab_ref, eps_fixed, reps):
+def bench_learned(cc, torch, gh, order, lab_ref, eps_fixed, reps, other_seeds=(32, 33)):
     """The learned eps policy against the fixed rule on the same graph and
     order: eps = 0.5 and every half-octave candidate eps of the trainer (the
-    best fixed eps in hindsight), for C4 and ClusterWild!."""
+    best fixed eps in hindsight), for C4 and ClusterWild!; then, for C4 on the
+    other evaluation orders, against eps = 0.5 with the labels compared."""
     import numpy as np
     from paper_1507_05086_amd import policy
     w, lo, hi = policy.load()
@@ -243,6 +244,26 @@ def bench_learned(cc, torch, gh, order, lab_ref, eps_fixed, reps):
         if name == "c4":
             r["labels_identical"] = bool(torch.equal(lab, lab_ref))
         out[name] = r
+    # the other evaluation orders: C4 under the policy against the fixed rule
+    import graphgen
+    others = {}
+    for seed in other_seeds:
+        o = torch.from_numpy(graphgen.permutation(order.numel(), seed)).to(order.device)
+        ref = torch.empty_like(lab_ref)
+        cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+        tf = [timed_call(cc, torch, cc.cc_c4, gh, o, eps_fixed, ref) for _ in range(reps)]
+        cc.cc_set_eps_policy(cc.CC_EPS_LEARNED, w, lo, hi)
+        try:
+            tl = [timed_call(cc, torch, cc.cc_c4, gh, o, 0.5, lab) for _ in range(reps)]
+        finally:
+            cc.cc_set_eps_policy(cc.CC_EPS_FIXED)
+        torch.cuda.synchronize()
+        fixed_ms, learned_ms = min(t for _, t in tf), min(t for _, t in tl)
+        others[str(seed)] = {"fixed_ms": round(fixed_ms, 3), "fixed_rounds": tf[-1][0].rounds,
+                             "learned_ms": round(learned_ms, 3), "learned_rounds": tl[-1][0].rounds,
+                             "speedup_vs_fixed": round(fixed_ms / learned_ms, 3),
+                             "labels_identical": bool(torch.equal(lab, ref))}
+    out["c4_other_orders"] = others
     return out
 
 
