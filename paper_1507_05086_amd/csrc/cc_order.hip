@@ -437,17 +437,17 @@ OrderMap order_map_layout(int64_t n, void *base) {
 
 hipError_t launch_order_map(const OrderMap &m, const int32_t *order_in, const int32_t *perm, int64_t n,
                             int32_t *iorder, Ctrl *ctrl, hipStream_t s, int32_t *rank) {
-  static hipError_t attr = [] {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_om_scatter),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)OM_SCATTER_LDS);
-    if (e != hipSuccess) return e;
+  // the LDS these kernels take beyond 64 KB, set for the current device on
+  // every launch (a few microseconds; nothing cached across devices or errors)
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_om_scatter),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)OM_SCATTER_LDS);
+  if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_om_gather), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)OM_GATHER_LDS);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_om_place), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)OM_PLACE_LDS);
-  }();
-  if (attr != hipSuccess) return attr;
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_om_place), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)OM_PLACE_LDS);
+  if (e != hipSuccess) return e;
   if (!order_map_applies(n) || m.nk != (int)((n + OM_SIZE - 1) / OM_SIZE) || m.nv != m.nk) return hipErrorInvalidValue;
   const unsigned tiles = (unsigned)(m.nkt * m.nvt);
   hipLaunchKernelGGL(k_om_count, dim3(m.nk), dim3(OM_BS), 0, s, m, order_in, n, ctrl);
