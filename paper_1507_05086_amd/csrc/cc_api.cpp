@@ -101,6 +101,8 @@ struct Workspace {
   int64_t trace_cap = 0;
   int32_t *order_buf = nullptr, *label_buf = nullptr, *iorder = nullptr;
   uint8_t *omap_buf = nullptr;  // bucketed order mapping scratch (large n only)
+  int32_t *ccol = nullptr;       // rows compacted at the switch to exact degrees (single graphs; col-sized)
+  int64_t *cend = nullptr;       // their ends
   OrderMap omap{};
   int64_t *sched = nullptr;
   int64_t sched_cap = 0;
@@ -169,7 +171,7 @@ void free_ws(Workspace &w) {
   void *ptrs[] = {w.rank, w.lab, w.ub, w.unc, w.state, w.flag, w.alist, w.clist, w.nlist, w.blist,
                   w.awork, w.cwork, w.rlist, w.xlist, w.rwork, w.xwork, w.racc, w.lvl, w.hist, w.plist, w.pwork,
                   w.cedge, w.tstat, w.ctrl, w.trace, w.order_buf, w.label_buf, w.sched, w.mlp, w.ainfo, w.cinfo,
-                  w.iorder, w.cost_size, w.cost_acc, w.dev_err, w.bpos, w.bpend, w.bdec, w.bdep, w.bq, w.bradj, w.omap_buf};
+                  w.iorder, w.cost_size, w.cost_acc, w.dev_err, w.bpos, w.bpend, w.bdec, w.bdep, w.bq, w.bradj, w.omap_buf, w.ccol, w.cend};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (w.host_flags) (void)hipHostFree(w.host_flags);
@@ -256,6 +258,10 @@ int32_t ensure_ws(cc_graph *g) {
   if (order_map_applies(n)) {
     HIP_TRY(dalloc(&w.omap_buf, order_map_bytes(n)));
     w.omap = order_map_layout(n, w.omap_buf);
+  }
+  if (g->rcol) {
+    HIP_TRY(dalloc(&w.ccol, (size_t)(g->nnz > 0 ? g->nnz : 1)));
+    HIP_TRY(dalloc(&w.cend, n));
   }
   HIP_TRY(dalloc(&w.mlp, CC_MLP_PARAMS));
   HIP_TRY(dalloc(&w.cost_size, n));
@@ -390,7 +396,10 @@ int32_t run_loop(cc_graph *g, int algo, const int32_t *order, double eps, int32_
   Ws w;
   std::memset(&w, 0, sizeof(w));  // the bytes (padding included) key the captured round graphs
   w.off = g->roff;
+  w.rend = g->roff + 1;
   w.col = g->rcol;
+  w.xcol = ws.ccol;
+  w.xend = ws.cend;
   w.n = n;
   w.order = ws.iorder;
   w.iorder = ws.iorder;

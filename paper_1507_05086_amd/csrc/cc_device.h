@@ -162,9 +162,15 @@ struct RowInfo {
 };
 
 struct Ws {
-  // graph
+  // graph: the full renumbered rows are col[off[v] .. rend[v]) (rend = off +
+  // 1).  The switch to exact degrees writes compacted rows, xcol[off[v] ..
+  // xend[v]), holding only the neighbours then unclustered, at the start of
+  // each row's original slot; every round after the switch walks those.
   const int64_t *off;
+  const int64_t *rend;
   const int32_t *col;
+  int32_t *xcol;        // compacted rows (col-sized; written at the switch)
+  int64_t *xend;        // their ends (n)
   int64_t n;
   int64_t max_deg;
   int64_t low_start;        // internal ids from here on have degree < DSW ...

@@ -109,7 +109,7 @@ __device__ inline bool row_contains(const int64_t *off, const int32_t *col, int6
 }
 
 __global__ void __launch_bounds__(BS) k_check(CheckArgs a) {
-  lb_walk(nullptr, a.wall, a.n, a.wall[a.n], a.off, a.col, nullptr, nullptr, [&](Items &it) {
+  lb_walk(nullptr, a.wall, a.n, a.wall[a.n], a.off, a.off + 1, a.col, nullptr, nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
       if (!(it.edge >> k & 1)) continue;
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(BS) k_plain_scan_local(const int64_t *x_in, in
 __global__ void __launch_bounds__(BS) k_relabel_cols(const int64_t *off, const int32_t *col, const int64_t *wall,
                                                      int64_t n, const int32_t *perm, const int64_t *roff,
                                                      int32_t *rcol) {
-  lb_walk(nullptr, wall, n, wall[n], off, col, perm, nullptr, [&](Items &it) {
+  lb_walk(nullptr, wall, n, wall[n], off, off + 1, col, perm, nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
       if (!(it.edge >> k & 1)) continue;
@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(BS) k_cost_sizes(CostArgs a) {
 __global__ void __launch_bounds__(BS) k_cost_same(CostArgs a) {
   int g_cur = -1;
   long long run = 0;
-  lb_walk(nullptr, a.wall, a.n, a.wall[a.n], a.off, a.col, a.labels, nullptr, [&](Items &it) {
+  lb_walk(nullptr, a.wall, a.n, a.wall[a.n], a.off, a.off + 1, a.col, a.labels, nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
       if (!(it.edge >> k & 1)) continue;

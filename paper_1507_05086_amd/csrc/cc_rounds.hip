@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(BS) k_dscan(Ws w) {
       const int32_t v = w.lvl[w.lvl_off[k] + (i - base[k])];
       const int32_t x = w.ub[v];
       if (x >= s.L && level_of(x) == k && unc_bit(w.unc, v))  // live entry, inside the band
-        stage_push(sb, v, (int32_t)(w.off[v + 1] - w.off[v]));
+        stage_push(sb, v, (int32_t)(w.rend[v] - w.off[v]));
     }
     __syncthreads();
     if (sb.cnt > BS) stage_flush(sb, &c->r_pack[IT], w.rlist + IT * w.rcap, w.rwork + IT * w.rcap, w.racc + IT * w.rcap);
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(BS) k_rescan(Ws w) {
     }
   };
   lb_walk(
-      w.rlist + IT * w.rcap, w.rwork + IT * w.rcap, cnt, pk_work(rp), w.off, w.col, nullptr, nullptr,
+      w.rlist + IT * w.rcap, w.rwork + IT * w.rcap, cnt, pk_work(rp), w.off, w.rend, w.col, nullptr, nullptr,
       [&](Items &it) {
 #pragma unroll
         for (int k = 0; k < IPT; k++)
@@ -351,6 +351,7 @@ __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
     const int64_t v = vb + threadIdx.x;
     if (v < v1 && unc_bit(w.unc, (int32_t)v)) {
       const int64_t d = w.off[v + 1] - w.off[v];
+      w.xend[v] = w.off[v];  // k_xcount appends the row's unclustered neighbours
       if (d > 0) stage_push(sb, (int32_t)v, (int32_t)d);
     }
     __syncthreads();
@@ -362,7 +363,12 @@ __global__ void __launch_bounds__(BS) k_xlist(Ws w) {
 // ... and count their unclustered neighbours into ub and the histogram: the
 // listed rows edge-balanced, the rows of degree below DSW (ids low_start ..
 // iso_start, by falling level) one lane per row, so a wave's rows are of
-// about one length and no search or barrier is needed.
+// about one length and no search or barrier is needed.  The unclustered
+// neighbours found are also written to the compacted rows (xcol, from the
+// start of each row's slot; xend = where the row ends): every vertex the
+// exact rounds walk is unclustered now, and its neighbours clustered before
+// now can never count again.  A listed row's tiles reserve their shares of
+// the slot with one atomic each, so its entries are in no particular order.
 __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
   Ctrl *c = w.ctrl;
   const CtrlHead h = ctrl_head(c);
@@ -370,6 +376,7 @@ __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
   const DSearch s = dsearch(&h, DITER);
   if (!s.switching) return;
   __shared__ int lcnt[TW];
+  __shared__ int64_t lbase[TW];  // where this tile's share of its row j goes in xcol
   __shared__ int s_hist[HLDS];
   for (int i = threadIdx.x; i < TW; i += BS) lcnt[i] = 0;
   for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
@@ -381,18 +388,36 @@ __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
     if (r > 0 && r < HLDS) atomicAdd(&s_hist[r], 1);
     else if (r >= HLDS) atomicAdd(&w.hist[r], 1);
   };
+  // this thread's unclustered neighbours in the current tile: the neighbour,
+  // its row's slot in the tile, and its index in the tile's share of the row
+  int32_t pu[IPT];
+  int pj[IPT], pl[IPT];
+  unsigned pending = 0;
   lb_walk(
-      w.xlist, w.xwork, pk_cnt(xp), pk_work(xp), w.off, w.col, nullptr, nullptr,
+      w.xlist, w.xwork, pk_cnt(xp), pk_work(xp), w.off, w.off + 1, w.col, nullptr, nullptr,
       [&](Items &it) {
+        pending = 0;
 #pragma unroll
         for (int k = 0; k < IPT; k++)
-          if ((it.edge >> k & 1) && unc_bit(w.unc, it.u[k])) atomicAdd(&lcnt[it.ent[k]], 1);
+          if ((it.edge >> k & 1) && unc_bit(w.unc, it.u[k])) {
+            pu[k] = it.u[k];
+            pj[k] = it.ent[k];
+            pl[k] = atomicAdd(&lcnt[it.ent[k]], 1);
+            pending |= 1u << k;
+          }
       },
       [&](int j, int64_t slot, int32_t v, int32_t deg, int64_t covered) {
         const int cj = lcnt[j];
         lcnt[j] = 0;
+        lbase[j] = cj > 0 ? (int64_t)atomicAdd((unsigned long long *)&w.xend[v], (unsigned long long)cj) : 0;
         int total = cj;
         if (covered == deg || row_combine(xacc, slot, cj, covered, deg, &total)) finalize(v, total);
+      },
+      [&]() {
+        __syncthreads();  // every row of the tile has its share reserved
+#pragma unroll
+        for (int k = 0; k < IPT; k++)
+          if (pending >> k & 1) w.xcol[lbase[pj[k]] + pl[k]] = pu[k];
       });
   static_assert(DSW <= HLDS, "a lower-degree row's count fits the LDS histogram");
   int64_t scanned = 0;
@@ -408,10 +433,11 @@ __global__ void __launch_bounds__(BS) k_xcount(Ws w) {
       for (int q = 0; q < 4; q++) u[q] = j + q < d ? w.col[s0 + j + q] : -1;
 #pragma unroll
       for (int q = 0; q < 4; q++)
-        if (u[q] >= 0 && unc_bit(w.unc, u[q])) r++;
+        if (u[q] >= 0 && unc_bit(w.unc, u[q])) w.xcol[s0 + r++] = u[q];
     }
     scanned += d;
     w.ub[v] = r;
+    w.xend[v] = s0 + r;
     if (r > 0) atomicAdd(&s_hist[r], 1);
   }
   const int64_t wsc = wave_sum(scanned);
@@ -463,6 +489,12 @@ __device__ inline long long lookback(const Ws &w, unsigned t) {
   return excl;
 }
 
+// The rows a round walks: the full rows until the run switches to exact
+// degrees, the rows the switch compacted after it (the phase is read at the
+// start of each kernel and changes only at the end of a round, in k_close).
+__device__ inline const int64_t *round_end(const Ws &w, int phase) { return phase == PHASE_EXACT ? w.xend : w.rend; }
+__device__ inline const int32_t *round_col(const Ws &w, int phase) { return phase == PHASE_EXACT ? w.xcol : w.col; }
+
 // The positions of this thread's slots marked in `act` hold this round's
 // active vertices (vv[k] at position base + k).  An active vertex with no
 // unclustered neighbour (degree 0, or an exact remaining degree of 0) is a
@@ -473,6 +505,7 @@ __device__ inline long long lookback(const Ws &w, unsigned t) {
 // cleared and no label).  The others go to the active list with their row
 // info.  Collective: every thread of the workgroup calls it.
 __device__ inline void activate(const Ws &w, Ctrl *c, const int32_t vv[SIPT], unsigned act, int64_t base, bool exact,
+                                const int64_t *rend,
                                 int64_t *sh, unsigned long long *s_base) {
   int64_t wsum = 0;
   int cnt = 0, lone = 0;
@@ -495,7 +528,7 @@ __device__ inline void activate(const Ws &w, Ctrl *c, const int32_t vv[SIPT], un
         clears++;
       } else {
         rs[k] = w.off[v];
-        wt[k] = (int32_t)(w.off[v + 1] - rs[k]);
+        wt[k] = (int32_t)(rend[v] - rs[k]);
         listed |= 1u << k;
         cnt++;
         wsum += wt[k];
@@ -617,7 +650,7 @@ __global__ void __launch_bounds__(SEL_BS) k_select(Ws w) {
         r++;
       }
     }
-    activate(w, c, vv, act, base, exact, sh, &s_base);
+    activate(w, c, vv, act, base, exact, round_end(w, h.phase), sh, &s_base);
     if (excl + agg >= B) break;
     __syncthreads();
   }
@@ -638,7 +671,7 @@ __global__ void __launch_bounds__(SEL_BS) k_select_range(Ws w) {
     const int64_t base = cur0 + t * TSEL + (int64_t)threadIdx.x * SIPT;
     int32_t vv[SIPT];
     const unsigned un = load_slots(w, base, end, vv);
-    activate(w, c, vv, un, base, false, sh, &s_base);
+    activate(w, c, vv, un, base, false, round_end(w, h.phase), sh, &s_base);
     __syncthreads();
   }
 }
@@ -650,7 +683,8 @@ __global__ void __launch_bounds__(BS) k_elect(Ws w) {
   const CtrlHead h = ctrl_head(c);
   if (h.done) return;
   const unsigned long long ap = h.a_pack;
-  lb_walk(w.alist, w.awork, pk_cnt(ap), pk_work(ap), w.off, w.col, nullptr, w.ainfo, [&](Items &it) {
+  lb_walk(w.alist, w.awork, pk_cnt(ap), pk_work(ap), w.off, round_end(w, h.phase), round_col(w, h.phase), nullptr,
+          w.ainfo, [&](Items &it) {
     uint8_t su[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; k++) su[k] = (it.edge >> k & 1) ? w.state[it.u[k]] : (uint8_t)UNCL;
@@ -729,7 +763,7 @@ __device__ inline void mark_decided(Ws &w, int32_t i, unsigned *tail) {
 // earlier neighbours are all decided, level by level.  Every blocked vertex
 // enters the queue once, when it is decided, and then walks its later
 // neighbours once: O(blocked + conflict edges) work, one barrier per level.
-__device__ void resolve_listed(Ws &w, Ctrl *c, int64_t nb, int64_t ne) {
+__device__ void resolve_listed(Ws &w, Ctrl *c, int64_t nb, int64_t ne, const int64_t *rend) {
   __shared__ unsigned s_tail;
   __shared__ int64_t sh[RBS / 64 + 1];
   __shared__ int64_t s_carry;
@@ -826,7 +860,7 @@ __device__ void resolve_listed(Ws &w, Ctrl *c, int64_t nb, int64_t ne) {
     }
     RowInfo ri{0, 0, 0};
     if (promote) {
-      ri = RowInfo{w.off[a], (int32_t)(w.off[a + 1] - w.off[a]), w.rank[a]};
+      ri = RowInfo{w.off[a], (int32_t)(rend[a] - w.off[a]), w.rank[a]};
       w.state[a] = CENTER;
       w.lab[a] = ri.rank;
     }
@@ -838,7 +872,7 @@ __device__ void resolve_listed(Ws &w, Ctrl *c, int64_t nb, int64_t ne) {
 // until nothing changes (every earlier-ranked unclustered neighbour of an
 // active vertex is active).  Each sweep settles at least the lowest-ranked
 // undecided vertex.
-__device__ void resolve_rows(Ws &w, Ctrl *c, int64_t nb) {
+__device__ void resolve_rows(Ws &w, Ctrl *c, int64_t nb, const int64_t *rend, const int32_t *col) {
   __shared__ int s_any;
   for (int64_t iter = 0; iter <= nb; iter++) {
     if (threadIdx.x == 0) s_any = 0;
@@ -852,8 +886,8 @@ __device__ void resolve_rows(Ws &w, Ctrl *c, int64_t nb) {
         if (w.state[a] == ACTIVE) {
           const int32_t ra = w.rank[a];
           bool center_before = false, undecided_before = false;
-          for (int64_t e = w.off[a]; e < w.off[a + 1] && !center_before; e++) {
-            const int32_t u = w.col[e];
+          for (int64_t e = w.off[a]; e < rend[a] && !center_before; e++) {
+            const int32_t u = col[e];
             if (!unc_bit(w.unc, u)) continue;
             const uint8_t su = w.state[u];
             if ((su == CENTER || su == ACTIVE) && w.rank[u] < ra) {
@@ -868,7 +902,7 @@ __device__ void resolve_rows(Ws &w, Ctrl *c, int64_t nb) {
       }
       RowInfo ri{0, 0, 0};
       if (promote) {
-        ri = RowInfo{w.off[a], (int32_t)(w.off[a + 1] - w.off[a]), w.rank[a]};
+        ri = RowInfo{w.off[a], (int32_t)(rend[a] - w.off[a]), w.rank[a]};
         w.state[a] = CENTER;
         w.lab[a] = ri.rank;
       }
@@ -886,8 +920,8 @@ __global__ void __launch_bounds__(RBS) k_resolve(Ws w) {
   const int64_t nb = h.n_blocked;
   if (nb == 0) return;
   const int64_t ne = h.n_cedges;
-  if (ne <= w.cedge_cap) resolve_listed(w, c, nb, ne);
-  else resolve_rows(w, c, nb);
+  if (ne <= w.cedge_cap) resolve_listed(w, c, nb, ne, round_end(w, h.phase));
+  else resolve_rows(w, c, nb, round_end(w, h.phase), round_col(w, h.phase));
   __syncthreads();
   for (int64_t i = threadIdx.x; i < nb; i += RBS) w.flag[w.blist[i]] = 0;
 }
@@ -910,7 +944,7 @@ __global__ void __launch_bounds__(BS) k_claim(Ws w) {
   if (threadIdx.x == 0) s_atom = 0;
   id_init(sb);
   lb_walk(
-      list, work, pk_cnt(lp), pk_work(lp), w.off, w.col, nullptr, info,
+      list, work, pk_cnt(lp), pk_work(lp), w.off, round_end(w, h.phase), round_col(w, h.phase), nullptr, info,
       [&](Items &it) {
         bool un[IPT];
 #pragma unroll
@@ -970,6 +1004,7 @@ __global__ void __launch_bounds__(BS) k_clear(Ws w) {
   for (int i = threadIdx.x; i < HLDS; i += BS) s_hist[i] = 0;
   stage_init(sp);
   const bool cw = w.algo == ALGO_CW, exact = h.phase == PHASE_EXACT;
+  const int64_t *rend = round_end(w, h.phase);
   const int64_t nc = pk_cnt(cw ? h.a_pack : h.c_pack);
   const int32_t *centers = cw ? w.alist : w.clist;
   const int64_t nn = nc + pk_cnt(h.n_pack);
@@ -989,7 +1024,7 @@ __global__ void __launch_bounds__(BS) k_clear(Ws w) {
       if (exact) {
         const int32_t d = w.ub[u];
         if (center) hist_add(s_hist, w.hist, d, -1);
-        else if (d > 0) stage_push(sp, u, (int32_t)(w.off[u + 1] - w.off[u]));
+        else if (d > 0) stage_push(sp, u, (int32_t)(rend[u] - w.off[u]));
       }
     }
     __syncthreads();
@@ -1025,7 +1060,8 @@ __global__ void __launch_bounds__(BS) k_peel(Ws w) {
   if (threadIdx.x == 0) s_atom = 0;
   __syncthreads();
   const unsigned long long pp = h.p_pack;
-  lb_walk(w.plist, w.pwork, pk_cnt(pp), pk_work(pp), w.off, w.col, nullptr, nullptr, [&](Items &it) {
+  lb_walk(w.plist, w.pwork, pk_cnt(pp), pk_work(pp), w.off, round_end(w, h.phase), round_col(w, h.phase), nullptr,
+          nullptr, [&](Items &it) {
 #pragma unroll
     for (int k = 0; k < IPT; k++)
       if (it.vert >> k & 1) hist_add(s_hist, w.hist, w.ub[it.v[k]], -1);  // the vertex leaves

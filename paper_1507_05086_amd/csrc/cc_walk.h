@@ -46,8 +46,9 @@ struct NoPost {
 };
 
 // Calls f(Items&) once per tile in every thread of the workgroup (uniformly,
-// so f may use wave-wide operations).  `vals` (may be null) is gathered per
-// row into Items::val.  A null `list` means the rows 0..cnt-1 themselves.
+// so f may use wave-wide operations).  Row v is col[off[v] .. end[v]) (end =
+// off + 1 for a plain CSR).  `vals` (may be null) is gathered per row into
+// Items::val.  A null `list` means the rows 0..cnt-1 themselves.
 // With `info` (per list entry), rows come from it and Items::val is the rank.
 // After f, ep(j, slot, v, deg, covered) runs once for every row j the tile
 // touched (slot = list index, covered = items of that row in this tile), so
@@ -55,7 +56,8 @@ struct NoPost {
 // post() runs in every thread (it may use barriers).
 template <class F, class E = NoEpilogue, class P = NoPost>
 __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restrict__ work, int64_t cnt,
-                        int64_t total, const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                        int64_t total, const int64_t *__restrict__ off, const int64_t *__restrict__ end,
+                        const int32_t *__restrict__ col,
                         const int32_t *__restrict__ vals, const RowInfo *__restrict__ info, F &&f, E &&ep = E(),
                         P &&post = P()) {
   __shared__ int64_t lw[TW + 1];
@@ -130,7 +132,7 @@ __device__ void lb_walk(const int32_t *__restrict__ list, const int64_t *__restr
       } else {
         const int64_t o = off[v];
         loff[j] = o;
-        ldeg[j] = (int32_t)(off[v + 1] - o);
+        ldeg[j] = (int32_t)(end[v] - o);
         lval[j] = vals ? vals[v] : 0;
       }
     }
