@@ -126,6 +126,11 @@ typedef struct cc_run_stats {
  *   out         receives the handle.
  * Column ranges are always checked (CC_ERR_OUT_OF_RANGE); CC_VALIDATE adds
  * the symmetry, self-loop and duplicate/sort checks.
+ * Device memory: a single graph (num_graphs == 1) also keeps a renumbered
+ * copy of its CSR (one more column array, 24 bytes per vertex), and its
+ * first run allocates a workspace of one column array plus about 170 bytes
+ * per vertex (about 20 GB at n = 2^26 with 2.1 G stored entries), held until
+ * destroy.  An allocation failure returns CC_ERR_OUT_OF_MEMORY.
  */
 CC_API int32_t cc_graph_from_csr(int32_t num_graphs, const int64_t *vtx_ptr, int64_t n_total,
                           const int64_t *offsets, const int32_t *cols, uint32_t flags,
