@@ -259,7 +259,7 @@ int32_t ensure_ws(cc_graph *g) {
     HIP_TRY(dalloc(&w.omap_buf, order_map_bytes(n)));
     w.omap = order_map_layout(n, w.omap_buf);
   }
-  if (g->rcol) {
+  if (g->num_graphs == 1) {  // the round loop's compacted rows (written at its switch to exact degrees)
     HIP_TRY(dalloc(&w.ccol, (size_t)(g->nnz > 0 ? g->nnz : 1)));
     HIP_TRY(dalloc(&w.cend, n));
   }
